@@ -1,0 +1,40 @@
+"""Plain FP64 CPU oracle for the scattered-wave-function (SWF) hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+runs this package; only the tests, the smoke check and the benchmark's CPU
+baseline leg do.  It shares no code with the HIP path: the only thing both
+sides consume is the data-only input module ``swf_workloads``.
+
+What it computes (arXiv 2512.16889, "Solving the Dirac equation on a GPU for
+strong-field processes in multidimensional background fields"):
+
+* ``dirac``       gamma matrices, free spinors u_s / v_s of eq. (uv) with the
+                  R_s of eq. (Reqs), free Hamiltonian and energy projectors
+                  (the Lambda matrices of eq. (LambdaDef)), photon
+                  polarisation basis of eq. (epsParaPerp).
+* ``lattice``     periodic grid, FFT wavenumbers (section "Numerical approach").
+* ``field``       separable background potentials A_mu(t, x), including the
+                  paper's single/double-peak examples, eqs. (singleE), (doubleE).
+* ``swf``         the inhomogeneous Dirac equation for the scattered wave,
+                  eq. (scatDirac), discretised pseudo-spectrally in space and
+                  integrated from t_out back to t_in with classical RK4.
+* ``observables`` inner products at t_in: the pair amplitude of eq. (Nmn)
+                  in both of its forms, electron/positron marginals,
+                  norm/orthogonality diagnostics.
+* ``bw``          nonlinear Breit-Wheeler amplitude: the finite-time vertex
+                  overlap of eq. (Mabfinite) integrated as an augmented
+                  state (the Y = (psi, M) construction of the BW numerical
+                  section) plus the analytic asymptotic-past terms
+                  (eq. (MScatScatPast) and its two single-mode partners).
+
+Pins (tests/test_oracle_*.py, all ``-m "not gpu"``) tie every function to
+something other than itself: Clifford algebra and spinor identities, the
+closed-form pure-gauge scattered wave, the Sauter-pulse pair spectrum,
+brute-force full-wave-function evolution with scipy's DOP853, unitarity and
+orthogonality identities, charge-conjugation symmetry, RK4 convergence
+order, the exact spin structure of the BW amplitude for E(t,x) fields and
+the t_in independence of past + finite BW terms.
+
+Parity unpinned: the absorbing-boundary mask (not part of the paper; it is
+off for every pin and parity case) has only a self-consistency check.
+"""

@@ -1,0 +1,330 @@
+"""Seeded synthetic inputs for the scattered-wave-function (SWF) solver.
+
+This module holds *data only*: the problem description (grid, time window,
+background-field descriptors, momenta/spins, photon vertices) and the seeded
+generators that draw the workloads' parameters.  It contains none of the
+method's arithmetic (no spinors, no field evaluation, no time stepping), so
+both the CPU oracle and the GPU library's binding can consume it without
+sharing any computation.
+
+Conventions of the descriptors (units m = c = hbar = 1, charge absorbed in A):
+
+* A field is a list of separable terms.  A term adds
+  ``amp * f_t(t) * f_x(x) * f_y(y) * f_z(z)`` to the *covariant* component
+  ``A_mu`` (mu = 0 is the scalar potential, A_j = -A^j).
+* A profile is ``env((s - c) / w) * cos(k * s + phi)`` with ``env`` one of the
+  PROF_* shapes below (``CONST`` ignores c and w).
+* A grid has ``dim`` non-trivial spatial axes (x; x,y; x,y,z), ``n[j]`` points
+  on the periodic interval ``[-L[j]/2, L[j]/2)``.  Axes j >= dim are trivial:
+  the field does not depend on them and their momentum is conserved.
+* A solve is an out-state U_out(s, p) (kind 0) or V_out(s, p) (kind 1), with
+  p the contravariant 3-momentum.
+* A vertex pairs one U solve and one V solve with a photon of 3-momentum k
+  (k^0 = |k|) and polarisation 3-vector eps (eps_mu = (0, eps)).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field as dc_field
+from typing import List, Sequence
+
+import numpy as np
+
+PROF_CONST = 0
+PROF_GAUSS = 1   # exp(-u^2)
+PROF_SECH2 = 2   # sech(u)^2
+PROF_TANH = 3    # tanh(u)
+PROF_UGAUSS = 4  # u * exp(-u^2)
+
+U_OUT = 0
+V_OUT = 1
+
+
+@dataclass
+class Profile:
+    type: int = PROF_CONST
+    c: float = 0.0
+    w: float = 1.0
+    k: float = 0.0
+    phi: float = 0.0
+
+
+def const() -> Profile:
+    return Profile(PROF_CONST)
+
+
+def gauss(w, c=0.0, k=0.0, phi=0.0) -> Profile:
+    return Profile(PROF_GAUSS, c, w, k, phi)
+
+
+def sech2(w, c=0.0, k=0.0, phi=0.0) -> Profile:
+    return Profile(PROF_SECH2, c, w, k, phi)
+
+
+def tanh(w, c=0.0, k=0.0, phi=0.0) -> Profile:
+    return Profile(PROF_TANH, c, w, k, phi)
+
+
+def ugauss(w, c=0.0, k=0.0, phi=0.0) -> Profile:
+    return Profile(PROF_UGAUSS, c, w, k, phi)
+
+
+@dataclass
+class Term:
+    mu: int
+    amp: float
+    ft: Profile
+    fx: List[Profile] = dc_field(default_factory=lambda: [const(), const(), const()])
+
+
+@dataclass
+class Grid:
+    dim: int
+    n: List[int]
+    L: List[float]
+    absorb_cells: int = 0
+    absorb_strength: float = 0.0
+
+    @property
+    def sites(self) -> int:
+        return int(np.prod(self.n[: self.dim]))
+
+
+@dataclass
+class Window:
+    t_in: float
+    t_out: float
+    dt: float
+
+    @property
+    def steps(self) -> int:
+        return int(round((self.t_out - self.t_in) / self.dt))
+
+
+@dataclass
+class Solve:
+    kind: int
+    spin: int
+    p: List[float]
+    grid: int = 0
+    field: int = 0
+
+
+@dataclass
+class Vertex:
+    u_solve: int
+    v_solve: int
+    k: List[float]
+    eps: List[float]
+
+
+@dataclass
+class Problem:
+    name: str
+    grids: List[Grid]
+    fields: List[List[Term]]
+    solves: List[Solve]
+    window: Window
+    vertices: List[Vertex] = dc_field(default_factory=list)
+
+    def site_updates(self, steps: int | None = None) -> int:
+        st = self.window.steps if steps is None else steps
+        return sum(self.grids[s.grid].sites for s in self.solves) * st
+
+
+# --------------------------------------------------------------------------
+# Field shapes of the workloads (descriptors only)
+# --------------------------------------------------------------------------
+
+def field_sech2_1d(E=0.3, omega=0.2, kappa=0.1) -> List[Term]:
+    """A_1(t,x) = (E/omega) sech^2(omega t) sech^2(kappa x)."""
+    return [Term(1, E / omega, sech2(1.0 / omega), [sech2(1.0 / kappa), const(), const()])]
+
+
+def field_gauss_2d(a0=1.0, tau=10.0, w=20.0, mu=1) -> List[Term]:
+    """A_mu(t,x,y) = a0 exp(-t^2/tau^2 - (x^2+y^2)/w^2)."""
+    return [Term(mu, a0, gauss(tau), [gauss(w), gauss(w), const()])]
+
+
+def field_sech2_gauss_3d(a0=0.8, tau=8.0, w=15.0, mu=3) -> List[Term]:
+    """A_mu(t,x,y,z) = a0 sech^2(t/tau) exp(-(x^2+y^2+z^2)/w^2)."""
+    return [Term(mu, a0, sech2(tau), [gauss(w), gauss(w), gauss(w)])]
+
+
+def field_pulse_3d(a0=1.0, tau=6.0, w=10.0, omega0=0.5, mu=1) -> List[Term]:
+    """A_mu = a0 exp(-t^2/tau^2 - |x|^2/w^2) cos(omega0 t): a focused pulse
+    that vanishes in every spacetime direction."""
+    return [Term(mu, a0, gauss(tau, k=omega0), [gauss(w), gauss(w), gauss(w)])]
+
+
+def field_single_e(E0, omega, kx, ky=0.0, kz=0.0, dim=1, shift=0.0) -> List[Term]:
+    """The paper's single-peak potential A_0 = -(E0/kx) sin(kx x) exp(-(omega t)^2
+    - (kx x)^2 - (ky y)^2 - (kz z)^2) (section 'Numerical examples'), optionally
+    shifted along x by ``shift``."""
+    fx = [gauss(1.0 / kx, c=shift, k=kx, phi=-np.pi / 2 - kx * shift)]
+    fx.append(gauss(1.0 / ky) if (dim >= 2 and ky > 0) else const())
+    fx.append(gauss(1.0 / kz) if (dim >= 3 and kz > 0) else const())
+    return [Term(0, -E0 / kx, gauss(1.0 / omega), fx)]
+
+
+def field_double_e(E0, omega, kx, ky, dx) -> List[Term]:
+    """Sum of two single-peak potentials shifted by +-dx (the 'doubleE' case)."""
+    return field_single_e(E0, omega, kx, ky, dim=2, shift=-dx) + \
+        field_single_e(E0, omega, kx, ky, dim=2, shift=+dx)
+
+
+def field_pure_gauge(lam0, tau, w, dim) -> List[Term]:
+    """A_mu = d_mu Lambda for Lambda = lam0 exp(-t^2/tau^2 - sum_j x_j^2/w^2).
+
+    The descriptor is written out term by term (A_0 = dLambda/dt,
+    A_j = dLambda/dx^j), so it is a field whose scattered wave has the closed
+    form (exp(-i Lambda) - 1) psi_back."""
+    g = [gauss(w) if j < dim else const() for j in range(3)]
+    terms = [Term(0, -2.0 * lam0 / tau, ugauss(tau), list(g))]
+    for j in range(dim):
+        fx = list(g)
+        fx[j] = ugauss(w)
+        terms.append(Term(j + 1, -2.0 * lam0 / w, gauss(tau), fx))
+    return terms
+
+
+def field_sauter_time(E0, tau) -> List[Term]:
+    """Time-only Sauter pulse E^x = E0 sech^2(t/tau) in the gauge
+    A_1 = E0 tau (tanh(t/tau) - 1), which vanishes at t -> +infinity."""
+    return [Term(1, E0 * tau, tanh(tau)), Term(1, -E0 * tau, const())]
+
+
+# --------------------------------------------------------------------------
+# Seeded momentum / parameter draws
+# --------------------------------------------------------------------------
+
+def momenta_in_disk(n: int, radius: float, seed: int = 0) -> np.ndarray:
+    """n momenta (px, py, 0) uniform in the disk |p| < radius."""
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.random(n))
+    th = 2.0 * np.pi * rng.random(n)
+    return np.stack([r * np.cos(th), r * np.sin(th), np.zeros(n)], axis=1)
+
+
+def random_state(shape, seed=0, scale=1.0) -> np.ndarray:
+    """Seeded random complex spinor field of the given shape (complex128)."""
+    rng = np.random.default_rng(seed)
+    return scale * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+# --------------------------------------------------------------------------
+# The five workload shapes.  Each takes size overrides so the parity tests
+# can run the same shape at sizes the oracle finishes in seconds.
+# --------------------------------------------------------------------------
+
+def config_1d(n=1024, L=200.0, dt=0.02, t_half=60.0, p=(0.5, 0.0, 0.0), spin=1,
+              steps=None) -> Problem:
+    """(1+1)D Schwinger: A_1 = (E/w) sech^2(w t) sech^2(k x), E=0.3, w=0.2, k=0.1."""
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    return Problem("1d_sech2", [Grid(1, [n, 1, 1], [L, 1.0, 1.0])], [field_sech2_1d()],
+                   [Solve(U_OUT, spin, list(p))], win)
+
+
+def config_2d(n=512, L=160.0, dt=0.02, t_half=60.0, n_solves=64, seed=0, steps=None) -> Problem:
+    """(2+1)D Schwinger: A_1 = exp(-t^2/100 - (x^2+y^2)/400), n x n grid over
+    [-80,80)^2, a batch of U_out(s=+1) solves with p uniform in |p| < 1."""
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    ps = momenta_in_disk(n_solves, 1.0, seed)
+    solves = [Solve(U_OUT, 1, list(map(float, p))) for p in ps]
+    return Problem("2d_gauss", [Grid(2, [n, n, 1], [L, L, 1.0])], [field_gauss_2d()], solves, win)
+
+
+def config_3d(n=256, L=120.0, dt=0.025, t_half=50.0, pz=(0.0, 0.25, 0.5, 0.75),
+              spins=(1, -1), steps=None) -> Problem:
+    """(3+1)D Schwinger: A_3 = 0.8 sech^2(t/8) exp(-|x|^2/225), n^3 grid."""
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    solves = [Solve(U_OUT, s, [0.0, 0.0, float(q)]) for q in pz for s in spins]
+    return Problem("3d_sech2_gauss", [Grid(3, [n, n, n], [L, L, L])], [field_sech2_gauss_3d()],
+                   solves, win)
+
+
+RAGGED_SIZES = (256, 384, 512, 768, 1024)
+
+
+def config_ragged_2d(n_solves=256, sizes=RAGGED_SIZES, L=160.0, dt=0.02, t_half=60.0, seed=0,
+                     steps=None) -> Problem:
+    """Batched uneven (2+1)D: grid sizes drawn uniformly from ``sizes``;
+    Gaussian-envelope fields with a0~U[0.5,1.5], tau~U[5,15], w~U[10,30]."""
+    rng = np.random.default_rng(seed)
+    n_pick = rng.choice(np.asarray(sizes), size=n_solves)
+    a0 = rng.uniform(0.5, 1.5, n_solves)
+    tau = rng.uniform(5.0, 15.0, n_solves)
+    w = rng.uniform(10.0, 30.0, n_solves)
+    ps = momenta_in_disk(n_solves, 1.0, seed + 1)
+    grids, gidx = [], {}
+    for n in sorted(set(int(v) for v in n_pick)):
+        gidx[n] = len(grids)
+        grids.append(Grid(2, [n, n, 1], [L, L, 1.0]))
+    fields, solves = [], []
+    for i in range(n_solves):
+        fields.append(field_gauss_2d(float(a0[i]), float(tau[i]), float(w[i])))
+        solves.append(Solve(U_OUT, 1, list(map(float, ps[i])), gidx[int(n_pick[i])], i))
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    return Problem("2d_ragged", grids, fields, solves, win)
+
+
+def config_bw_3d(n=320, L=120.0, dt=0.025, t_half=37.5, n_p=8, steps=None) -> Problem:
+    """(3+1)D nonlinear Breit-Wheeler: focused pulse a0=1, w=10, tau=6,
+    omega0=0.5; photon k = (0,0,2); eps_par for e = x-hat; pairs
+    p = (P,0,1), q = (-P,0,1), P in linspace(-0.7,0.7,n_p), 4 spin pairs."""
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    Ps = np.linspace(-0.7, 0.7, n_p)
+    solves, verts = [], []
+    k = [0.0, 0.0, 2.0]
+    eps = [-1.0, 0.0, 0.0]  # eps_par = (e x k) x k / |...| for e = x-hat, k along z
+    for P in Ps:
+        iu = {}
+        iv = {}
+        for s in (1, -1):
+            iu[s] = len(solves)
+            solves.append(Solve(U_OUT, s, [float(P), 0.0, 1.0]))
+        for r in (1, -1):
+            iv[r] = len(solves)
+            solves.append(Solve(V_OUT, r, [float(-P), 0.0, 1.0]))
+        for s in (1, -1):
+            for r in (1, -1):
+                verts.append(Vertex(iu[s], iv[r], list(k), list(eps)))
+    return Problem("3d_bw_pulse", [Grid(3, [n, n, n], [L, L, L])], [field_pulse_3d()], solves,
+                   win, verts)
+
+
+def config_bw_1d(P=0.3, n=512, L=240.0, dt=0.05, t_half=40.0, spins=((1, 1),),
+                 steps=None) -> Problem:
+    """(1+1)D Breit-Wheeler with the paper's Fig. 7 parameters: single-peak
+    field with -E0 = omega = 1/6, kx = omega/2; k = (0, 1.2, 0), p2 = q2 = 0.6,
+    p1 = -q1 = P; eps_par for e = x-hat (= -x-hat)."""
+    omega = 1.0 / 6.0
+    E0 = -omega
+    win = Window(-t_half, t_half, dt)
+    if steps is not None:
+        win = Window(t_half - steps * dt, t_half, dt)
+    solves, verts = [], []
+    k = [0.0, 1.2, 0.0]
+    eps = [-1.0, 0.0, 0.0]
+    for s, r in spins:
+        iu = len(solves)
+        solves.append(Solve(U_OUT, s, [float(P), 0.6, 0.0]))
+        iv = len(solves)
+        solves.append(Solve(V_OUT, r, [float(-P), 0.6, 0.0]))
+        verts.append(Vertex(iu, iv, list(k), list(eps)))
+    return Problem("1d_bw_single_e", [Grid(1, [n, 1, 1], [L, 1.0, 1.0])],
+                   [field_single_e(E0, omega, omega / 2)], solves, win, verts)
+
+
+def lattice_momentum(n: int, L: float, m: int) -> float:
+    """The m-th lattice wavenumber 2 pi m / L of an n-point periodic axis."""
+    return 2.0 * np.pi * m / L
