@@ -1,0 +1,207 @@
+/*
+ * swf.h -- C ABI of the MI355X scattered-wave-function (SWF) solver.
+ *
+ * Method: arXiv 2512.16889 (G. Torgrimsson), "Solving the Dirac equation on a
+ * GPU for strong-field processes in multidimensional background fields".
+ *
+ *   - The scattered wave psi_s of an out-state U_out(s,p) or V_out(s,p) solves
+ *     the inhomogeneous Dirac equation (i Dslash - 1) psi_s = Aslash psi_back,
+ *     eq. (scatDirac), with psi_s(t_out) = 0, where D_mu = d_mu + i A_mu and
+ *     psi_back = u_s(p) e^{-ipx} or v_s(p) e^{ipx} (section "Scattered wave
+ *     functions"; spinors of eq. (uv) with R_s of eq. (Reqs)).
+ *   - Space is discretised pseudo-spectrally on a periodic grid (section
+ *     "Numerical approach"); time is stepped with classical RK4, h = -dt,
+ *     from t_out back to t_in.
+ *   - At t_in the library forms the inner products of eq. (Nmn) (pair
+ *     amplitude and marginals) and the Breit-Wheeler vertex amplitude
+ *     M = M_finite + M_past of the section "Nonlinear Breit-Wheeler pair
+ *     production" (eqs. (Mabfinite), (MScatScatPast) and partners).
+ *
+ * Units: m = c = hbar = 1, the charge absorbed into A.  Metric (+,-,-,-).
+ * All host scalars are double; a complex number is double[2] = {re, im}.
+ *
+ * Threading: a context is not thread-safe; distinct contexts are independent.
+ * Errors: every call returns a status; nothing is thrown across the ABI.
+ * swf_last_error(ctx) returns the message of the context's last failure
+ * (swf_last_error(NULL) that of the last failed swf_init on this thread).
+ */
+#ifndef SWF_H
+#define SWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swf_ctx swf_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    SWF_OK = 0,
+    SWF_E_ARG = 1,         /* invalid argument (see each call)                      */
+    SWF_E_NOMEM = 2,       /* device allocation failed or workspace too small       */
+    SWF_E_HIP = 3,         /* a HIP runtime call failed                              */
+    SWF_E_ORDER = 4,       /* call out of order (e.g. amplitude before t_in)         */
+    SWF_E_UNSUPPORTED = 5, /* grid size / option not supported by this build         */
+    SWF_E_NONFINITE = 6    /* a NaN or Inf was detected in the state                 */
+} swf_status;
+
+typedef enum {
+    SWF_FP64 = 0,  /* state, FFTs and stepping in complex double                      */
+    SWF_MIXED = 1  /* state, FFTs and stepping in complex float; plane-wave phases,
+                      times, field time factors and every reduction in double       */
+} swf_precision;
+
+typedef enum { SWF_U_OUT = 0, SWF_V_OUT = 1 } swf_kind;
+
+/* Profile shapes: f(s) = env((s - c)/w) * cos(k s + phi). */
+enum {
+    SWF_PROF_CONST = 0,  /* env = 1 (c and w ignored)  */
+    SWF_PROF_GAUSS = 1,  /* env = exp(-u^2)            */
+    SWF_PROF_SECH2 = 2,  /* env = sech(u)^2            */
+    SWF_PROF_TANH = 3,   /* env = tanh(u)              */
+    SWF_PROF_UGAUSS = 4  /* env = u exp(-u^2)          */
+};
+
+typedef struct { int type; double c, w, k, phi; } swf_profile;
+
+/* One separable term of a background potential (section "Numerical examples"
+ * writes its fields this way): covariant A_mu(t,x,y,z) += amp * ft(t) *
+ * fx[0](x) * fx[1](y) * fx[2](z).  mu = 0 is the scalar potential, A_j = -A^j.
+ * fx[j] must be SWF_PROF_CONST (with k = phi = 0) on trivial axes j >= dim. */
+typedef struct { int mu; double amp; swf_profile ft; swf_profile fx[3]; } swf_term;
+
+/* Periodic grid of the pseudo-spectral discretisation (array (g, n_x, n_y, n_z)
+ * of section "Numerical approach", g = 4).  dim = number of non-trivial axes
+ * (x; x,y; x,y,z).  Axis j has n[j] points x_i = -L[j]/2 + i L[j]/n[j].
+ * Supported n: 16..1024 of the forms 2^a, 3*2^a, 5*2^a (see swf_supported_n).
+ * absorb_cells > 0 enables a boundary mask applied to psi_s after every step:
+ * m = 1 - absorb_strength * sin^2(pi/2 (cells - d)/cells) within `cells` of an
+ * edge (d = distance in cells).  The mask is not part of the paper's method. */
+typedef struct { int dim; int n[3]; double L[3]; int absorb_cells; double absorb_strength; } swf_grid;
+
+/* Time window shared by every solve of a context: steps = round((t_out - t_in)/dt).
+ * The field must be negligible before t_in and after t_out (eq. (Nmn) text). */
+typedef struct { double t_in, t_out, dt; } swf_window;
+
+/* One out-state solve: U_out(spin, p) (kind 0) or V_out(spin, p) (kind 1);
+ * p is the contravariant 3-momentum; spin = +1 or -1 labels R_s of eq. (Reqs).
+ * grid/field index the arrays given to swf_init. */
+typedef struct { int kind; int spin; double p[3]; int grid; int field; } swf_solve;
+
+/* Breit-Wheeler vertex: photon with 3-momentum k (k^0 = |k|) and polarisation
+ * eps (epsilon_mu = (0, eps), eq. (epsParaPerp) gives the usual basis).
+ * u_solve must be a U solve and v_solve a V solve on the same grid and field;
+ * on trivial axes p + q = k must hold. */
+typedef struct { int u_solve, v_solve; double k[3]; double eps[3]; } swf_vertex;
+
+typedef struct {
+    int prec;               /* swf_precision                                          */
+    void* stream;           /* hipStream_t the work is ordered with (NULL = null stream) */
+    void* workspace;        /* optional caller-owned device memory for every buffer     */
+    size_t workspace_bytes; /* its size; must be >= swf_workspace_size()                */
+    int use_graph;          /* 1: replay each time step as a captured hipGraph          */
+    int batched;            /* 1: one launch per pass for all solves of a grid size;
+                               0: separate launches per solve ("per-instance")          */
+    int profile;            /* 1: time every pass with HIP events (see swf_kernel_stats) */
+    int tune;               /* 1: autotune tile shapes at init (results cached)         */
+    const char* tune_cache; /* path of the tune cache file, or NULL                     */
+} swf_options;
+
+/* Device bytes swf_init needs for these inputs (tables, states, scratch). */
+swf_status swf_workspace_size(const swf_grid* grids, int n_grids, const swf_term* terms,
+                              const int* field_first_term, int n_fields, const swf_solve* solves,
+                              int n_solves, const swf_vertex* vertices, int n_vertices,
+                              const swf_window* window, const swf_options* opt, size_t* bytes);
+
+/* Validate, plan, allocate and upload.  Field f is terms[field_first_term[f] ..
+ * field_first_term[f+1]) (field_first_term has n_fields + 1 entries).  Inputs are
+ * deep-copied; all-or-nothing (on failure *out = NULL).
+ * SWF_E_ARG: bad sizes/indices, momentum beyond the grid's Nyquist wavenumber on a
+ * non-trivial axis, dt * E_max >= 2.8 (RK4 stability on the imaginary axis is
+ * 2 sqrt 2), a field depending on a trivial axis, an invalid vertex.
+ * SWF_E_UNSUPPORTED: a grid size without an FFT plan. */
+swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms,
+                    const int* field_first_term, int n_fields, const swf_solve* solves,
+                    int n_solves, const swf_vertex* vertices, int n_vertices,
+                    const swf_window* window, const swf_options* opt, swf_ctx** out);
+
+/* Enqueue n_steps RK4 steps of every solve (and of the BW vertex integrals)
+ * toward t_in on the context's stream.  Asynchronous: returns after enqueueing.
+ * *steps_left (optional) receives the remaining step count.
+ * SWF_E_ORDER if n_steps exceeds the steps left; SWF_E_ARG if n_steps < 0. */
+swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left);
+
+/* Wait for the context's queued work.  SWF_E_HIP on a device error. */
+swf_status swf_sync(swf_ctx* ctx);
+
+enum {
+    SWF_AMP_PAIR1 = 0, /* Omega(m,n), form 1 of eq. (Nmn): (U_b|V_s) + (U_s|Pi_+|V_s); i = U solve, j = V solve */
+    SWF_AMP_PAIR2 = 1, /* form 2: (U_s|V_b) + (U_s|Pi_-|V_s) (= -form 1 by orthogonality)                     */
+    SWF_AMP_BW = 2     /* BW amplitude of vertex i; j = -1 total, j = 0/1/2 the (s,s)/(b,s)/(s,b) term          */
+};
+/* Amplitudes at t_in (requires steps_left == 0, else SWF_E_ORDER).
+ * PAIR: coefficient of (2 pi)^(3-d) delta(p_perp + q_perp), d = dim; requires
+ * q_perp = -p_perp on trivial axes (else SWF_E_ARG).  BW: M per
+ * (2 pi)^(3-d) delta_perp(p + q - k), no phase-space or e^2 factors (Fig. 7). */
+swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]);
+
+enum {
+    SWF_P_MARGINAL_E = 0,   /* electron marginal (U_s|Pi_-|U_s) of U solve i           */
+    SWF_P_MARGINAL_POS = 1, /* positron marginal (V_s|Pi_+|V_s) of V solve i           */
+    SWF_P_PAIR = 2,         /* |Omega_1(i,j)|^2                                        */
+    SWF_P_BW = 3            /* |M|^2 of vertex i                                       */
+};
+/* Probabilities at t_in (SWF_E_ORDER before t_in).  Marginals are densities in
+ * d^d p/(2 pi)^d per unit transverse volume. */
+swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out);
+
+/* Diagnostics of solve i at the current time t = t_out - step*dt, accumulated in
+ * double: out[0] = (psi_s|psi_s), out[1] = 2 Re(psi_b|psi_s) (for a momentum on the
+ * lattice out[0] + out[1] stays 0: the full wave function keeps its norm),
+ * out[2] = max |psi_s component|, out[3] = 1 if every value is finite else 0.
+ * Returns SWF_E_NONFINITE if out[3] == 0. */
+swf_status swf_diagnostics(swf_ctx* ctx, int i, double out[4]);
+
+/* Copy the scattered wave of solve i to / from host memory as complex double,
+ * layout [component 0..3][z][y][x] (x fastest), 8 * n_sites doubles.  set_psi
+ * also sets the step index (0 <= step_index <= steps) and, for BW vertices that
+ * use the solve, leaves their accumulated M unchanged (use swf_set_bw_state).
+ * Both synchronise the context's stream. */
+swf_status swf_get_psi(swf_ctx* ctx, int i, double* host);
+swf_status swf_set_psi(swf_ctx* ctx, int i, const double* host, int step_index);
+
+/* Accumulated finite-time BW integrals of vertex i at the current step
+ * (3 complex: (s,s), (b,s), (s,b) of int_{t_out}^{t} dt' Mdot): get / set, for
+ * checkpoint and resume. */
+swf_status swf_get_bw_state(swf_ctx* ctx, int i, double out[6]);
+swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]);
+
+/* Test hook: apply one spatial operator to solve i's layout.  op 0: out = FFT of
+ * in over the non-trivial axes (unnormalised, numpy sign); op 1: out = the
+ * kinetic term IFFT(-i H0(k) FFT(in)) of the stepper; op 2: out = the full
+ * right-hand side F(t, in) at time t (kinetic + source).  in/out as swf_get_psi.
+ * Uses the solve's ACC/YS/T buffers: only valid before stepping or after t_in
+ * (SWF_E_ORDER otherwise). */
+swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in, double* out);
+
+/* Pass timing collected when options.profile = 1.  kind: 0 row pass (x axis,
+ * with the stage epilogue), 1 column pass (y axis), 2 column pass (z axis),
+ * 3 BW vertex reduction, 4 other.  Returns launches, summed device milliseconds
+ * and the algorithmic HBM bytes those launches move (state reads + writes). */
+swf_status swf_kernel_stats(swf_ctx* ctx, int kind, long long* launches, double* ms, double* bytes);
+swf_status swf_reset_stats(swf_ctx* ctx);
+
+/* 1 if n has an FFT plan in this build. */
+int swf_supported_n(int n);
+
+/* Total steps of the context's window; current step index. */
+swf_status swf_steps(swf_ctx* ctx, int* total, int* done);
+
+const char* swf_last_error(const swf_ctx* ctx);
+void swf_free(swf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWF_H */

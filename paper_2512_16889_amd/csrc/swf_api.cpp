@@ -1,0 +1,1362 @@
+// Host side of the SWF C ABI: validation, planning, table construction,
+// device memory layout, pass scheduling (eager, batched or per-instance, and
+// hipGraph replay), and the host-side FP64 arithmetic of the amplitudes.
+//
+// Method: arXiv 2512.16889.  Scattered waves solve eq. (scatDirac) backward
+// from t_out; at t_in the pair amplitude (eq. (Nmn)), the marginals and the
+// Breit-Wheeler amplitude (finite part eq. (Mabfinite) + past part
+// eq. (MScatScatPast) and partners) are formed from FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/swf.h"
+#include "swf_kernels.h"
+#include "swf_reduce.h"
+
+using swf::SolveDev;
+using swf::TermDev;
+using swf::VertexDev;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int RED_BLOCKS = 512;          // blocks of every reduction launch (fixed: deterministic sums)
+constexpr int BW_BLOCKS = 256;           // blocks per vertex of the BW stage reduction
+constexpr int PROF_POOL = 2048;          // event pairs kept in flight when profiling
+
+const double PI = 3.14159265358979323846;
+
+// ------------------------------------------------------------ host Dirac algebra
+struct Spinor { cd c[4]; };
+
+// sigma.p as 2x2
+static void sigma_dot(const double* p, cd m[2][2]) {
+    m[0][0] = p[2];
+    m[0][1] = cd(p[0], -p[1]);
+    m[1][0] = cd(p[0], p[1]);
+    m[1][1] = -p[2];
+}
+
+// u_s(p) = (1 + pslash) R_s / sqrt(2 p0 (p0 - p^1)), v_s(p) = (1 - pslash) R_s / same
+// (eq. (uv) with p_1 = -p^1; R_s = (1, s, s, 1)/2 from eq. (Reqs), Dirac representation).
+static Spinor free_spinor(int kind, int s, const double* p) {
+    const double E = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    const cd a[2] = {0.5, 0.5 * s}, b[2] = {0.5 * s, 0.5};
+    cd sp[2][2];
+    sigma_dot(p, sp);
+    const double sg = kind == 0 ? 1.0 : -1.0;   // u: 1 + pslash, v: 1 - pslash
+    // pslash = [[E, -sigma.p], [sigma.p, -E]]
+    Spinor r;
+    for (int i = 0; i < 2; ++i) {
+        cd spb = sp[i][0] * b[0] + sp[i][1] * b[1];
+        cd spa = sp[i][0] * a[0] + sp[i][1] * a[1];
+        r.c[i] = a[i] + sg * (E * a[i] - spb);
+        r.c[2 + i] = b[i] + sg * (spa - E * b[i]);
+    }
+    const double nrm = std::sqrt(2.0 * E * (E - p[0]));
+    for (auto& x : r.c) x /= nrm;
+    return r;
+}
+
+static Spinor h0_apply(const Spinor& p, const double* K) {
+    cd s[2][2];
+    sigma_dot(K, s);
+    Spinor o;
+    for (int i = 0; i < 2; ++i) {
+        o.c[i] = p.c[i] + s[i][0] * p.c[2] + s[i][1] * p.c[3];
+        o.c[2 + i] = s[i][0] * p.c[0] + s[i][1] * p.c[1] - p.c[2 + i];
+    }
+    return o;
+}
+
+static Spinor proj(const Spinor& p, const double* K, int sign) {
+    const double E = std::sqrt(1.0 + K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
+    Spinor h = h0_apply(p, K), o;
+    for (int q = 0; q < 4; ++q) o.c[q] = 0.5 * (p.c[q] + (double)sign * h.c[q] / E);
+    return o;
+}
+
+static Spinor gamma_eps(const Spinor& p, const double* e) {   // (alpha.eps) psi
+    cd s[2][2];
+    sigma_dot(e, s);
+    Spinor o;
+    for (int i = 0; i < 2; ++i) {
+        o.c[i] = s[i][0] * p.c[2] + s[i][1] * p.c[3];
+        o.c[2 + i] = s[i][0] * p.c[0] + s[i][1] * p.c[1];
+    }
+    return o;
+}
+
+static cd dot(const Spinor& a, const Spinor& b) {
+    cd s = 0;
+    for (int q = 0; q < 4; ++q) s += std::conj(a.c[q]) * b.c[q];
+    return s;
+}
+
+static double profile_h(const swf_profile& p, double s) {
+    double env = 1.0;
+    if (p.type != SWF_PROF_CONST) {
+        const double u = (s - p.c) / p.w;
+        switch (p.type) {
+            case SWF_PROF_GAUSS: env = std::exp(-u * u); break;
+            case SWF_PROF_SECH2: { const double ch = std::cosh(u); env = 1.0 / (ch * ch); } break;
+            case SWF_PROF_TANH: env = std::tanh(u); break;
+            default: env = u * std::exp(-u * u); break;
+        }
+    }
+    if (p.k != 0.0 || p.phi != 0.0) env *= std::cos(p.k * s + p.phi);
+    return env;
+}
+
+static bool supported_n(int n) {
+    switch (n) {
+        case 16: case 32: case 64: case 128: case 256: case 512: case 1024:
+        case 48: case 96: case 192: case 384: case 768:
+        case 40: case 80: case 160: case 320: return true;
+        default: return false;
+    }
+}
+
+// ------------------------------------------------------------ plan
+struct Group {
+    int grid;
+    std::vector<int> solves;
+    const swf::SizeKernels* k[3] = {nullptr, nullptr, nullptr};
+    size_t it_row = 0, it_coly = 0, it_colz = 0;  // offsets (int2) into the item array
+    int n_row = 0, n_coly = 0, n_colz = 0;
+};
+
+struct Plan {
+    int fp64 = 0;
+    size_t csize = 8, rsize = 4;
+    int steps = 0;
+    std::vector<swf_grid> grids;
+    std::vector<std::vector<swf_term>> fields;
+    std::vector<swf_solve> solves;
+    std::vector<swf_vertex> verts;
+    swf_window win{};
+    std::vector<SolveDev> hs;           // buf pointers filled after allocation (offsets meanwhile)
+    std::vector<TermDev> ht;
+    std::vector<VertexDev> hv;
+    std::vector<double> rtab;           // real tables (rounded to the state precision on upload)
+    std::vector<cd> ctab;               // complex tables
+    std::vector<Group> batched, single; // groups per grid / per solve
+    std::vector<int2> items;
+    size_t state_bytes = 0;             // all state arrays
+    // arena layout (byte offsets)
+    size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_rtab = 0, off_ctab = 0,
+           off_items = 0, off_step = 0, off_M = 0, off_part = 0, off_red = 0, total = 0;
+    std::vector<size_t> solve_off;      // state offset of each solve (bytes from off_state)
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define FAIL(code, ...)                                              \
+    do {                                                             \
+        char _b[512];                                                \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                       \
+        err = _b;                                                    \
+        return code;                                                 \
+    } while (0)
+
+static void add_items(Plan& P, Group& g, int fp64) {
+    const swf_grid& G = P.grids[g.grid];
+    const int n0 = G.n[0], n1 = G.dim >= 2 ? G.n[1] : 1, n2 = G.dim >= 3 ? G.n[2] : 1;
+    g.k[0] = swf::size_kernels(fp64, n0);
+    if (G.dim >= 2) g.k[1] = swf::size_kernels(fp64, n1);
+    if (G.dim >= 3) g.k[2] = swf::size_kernels(fp64, n2);
+    g.it_row = P.items.size();
+    const int rows = g.k[0]->row_rows;
+    for (int s : g.solves)
+        for (int tile = 0; tile < (n1 * n2 + rows - 1) / rows; ++tile) P.items.push_back(make_int2(s, tile));
+    g.n_row = (int)(P.items.size() - g.it_row);
+    if (G.dim >= 2) {
+        g.it_coly = P.items.size();
+        const int ntx = (n0 + g.k[1]->col_w - 1) / g.k[1]->col_w;
+        for (int s : g.solves)
+            for (int tile = 0; tile < ntx * n2; ++tile) P.items.push_back(make_int2(s, tile));
+        g.n_coly = (int)(P.items.size() - g.it_coly);
+    }
+    if (G.dim >= 3) {
+        g.it_colz = P.items.size();
+        const int ntx = (n0 + g.k[2]->col_w - 1) / g.k[2]->col_w;
+        for (int s : g.solves)
+            for (int tile = 0; tile < ntx * n1; ++tile) P.items.push_back(make_int2(s, tile));
+        g.n_colz = (int)(P.items.size() - g.it_colz);
+    }
+}
+
+static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_grids, const swf_term* terms,
+                      const int* ffirst, int n_fields, const swf_solve* solves, int n_solves,
+                      const swf_vertex* verts, int n_verts, const swf_window* win, const swf_options* opt) {
+    if (!grids || n_grids <= 0 || !solves || n_solves <= 0 || !win || !opt) FAIL(SWF_E_ARG, "missing inputs");
+    if (n_fields < 0 || (n_fields > 0 && (!ffirst || !terms))) FAIL(SWF_E_ARG, "bad field arrays");
+    if (n_verts < 0 || (n_verts > 0 && !verts)) FAIL(SWF_E_ARG, "bad vertex array");
+    if (opt->prec != SWF_FP64 && opt->prec != SWF_MIXED) FAIL(SWF_E_ARG, "unknown precision %d", opt->prec);
+    P.fp64 = opt->prec == SWF_FP64;
+    P.csize = P.fp64 ? 16 : 8;
+    P.rsize = P.fp64 ? 8 : 4;
+    // window
+    P.win = *win;
+    if (!(win->dt > 0) || !(win->t_out > win->t_in)) FAIL(SWF_E_ARG, "need dt > 0 and t_out > t_in");
+    const double span = win->t_out - win->t_in;
+    P.steps = (int)std::llround(span / win->dt);
+    if (P.steps < 1 || std::fabs(P.steps * win->dt - span) > 1e-9 * span)
+        FAIL(SWF_E_ARG, "(t_out - t_in)/dt = %.12g is not an integer step count", span / win->dt);
+    // grids
+    for (int g = 0; g < n_grids; ++g) {
+        swf_grid G = grids[g];
+        if (G.dim < 1 || G.dim > 3) FAIL(SWF_E_ARG, "grid %d: dim must be 1..3", g);
+        for (int j = 0; j < 3; ++j) {
+            if (j < G.dim) {
+                if (!supported_n(G.n[j])) FAIL(SWF_E_UNSUPPORTED, "grid %d: no FFT plan for n[%d] = %d", g, j, G.n[j]);
+                if (!(G.L[j] > 0)) FAIL(SWF_E_ARG, "grid %d: L[%d] must be > 0", g, j);
+            } else {
+                G.n[j] = 1;
+                G.L[j] = 1.0;
+            }
+        }
+        if (G.absorb_cells < 0 || (G.absorb_cells > 0 && (2 * G.absorb_cells >= G.n[0] ||
+                                                          (G.dim >= 2 && 2 * G.absorb_cells >= G.n[1]) ||
+                                                          (G.dim >= 3 && 2 * G.absorb_cells >= G.n[2]))))
+            FAIL(SWF_E_ARG, "grid %d: absorb_cells out of range", g);
+        if (G.absorb_cells > 0 && !(G.absorb_strength >= 0 && G.absorb_strength <= 1))
+            FAIL(SWF_E_ARG, "grid %d: absorb_strength must be in [0,1]", g);
+        P.grids.push_back(G);
+    }
+    // fields
+    for (int f = 0; f < n_fields; ++f) {
+        const int a = ffirst[f], b = ffirst[f + 1];
+        if (a < 0 || b < a) FAIL(SWF_E_ARG, "field %d: bad term range", f);
+        if (b - a > swf::MAX_TERMS) FAIL(SWF_E_UNSUPPORTED, "field %d: more than %d terms", f, swf::MAX_TERMS);
+        std::vector<swf_term> tl;
+        for (int i = a; i < b; ++i) {
+            const swf_term& t = terms[i];
+            if (t.mu < 0 || t.mu > 3) FAIL(SWF_E_ARG, "term %d: mu must be 0..3", i);
+            const swf_profile* ps[4] = {&t.ft, &t.fx[0], &t.fx[1], &t.fx[2]};
+            for (auto* p : ps) {
+                if (p->type < 0 || p->type > 4) FAIL(SWF_E_ARG, "term %d: unknown profile type %d", i, p->type);
+                if (p->type != SWF_PROF_CONST && !(p->w != 0)) FAIL(SWF_E_ARG, "term %d: profile width 0", i);
+            }
+            tl.push_back(t);
+        }
+        P.fields.push_back(tl);
+    }
+    // solves
+    for (int i = 0; i < n_solves; ++i) {
+        const swf_solve& s = solves[i];
+        if (s.kind != 0 && s.kind != 1) FAIL(SWF_E_ARG, "solve %d: kind must be 0 (U) or 1 (V)", i);
+        if (s.spin != 1 && s.spin != -1) FAIL(SWF_E_ARG, "solve %d: spin must be +1 or -1", i);
+        if (s.grid < 0 || s.grid >= n_grids) FAIL(SWF_E_ARG, "solve %d: bad grid index", i);
+        if (s.field < 0 || s.field >= n_fields) FAIL(SWF_E_ARG, "solve %d: bad field index", i);
+        const swf_grid& G = P.grids[s.grid];
+        for (const auto& t : P.fields[s.field])
+            for (int j = G.dim; j < 3; ++j)
+                if (t.fx[j].type != SWF_PROF_CONST || t.fx[j].k != 0 || t.fx[j].phi != 0)
+                    FAIL(SWF_E_ARG, "solve %d: its field depends on trivial axis %d", i, j);
+        double emax2 = 1.0;
+        for (int j = 0; j < 3; ++j) {
+            if (!std::isfinite(s.p[j])) FAIL(SWF_E_ARG, "solve %d: non-finite momentum", i);
+            if (j < G.dim) {
+                const double kny = PI * G.n[j] / G.L[j];
+                if (std::fabs(s.p[j]) >= kny) FAIL(SWF_E_ARG, "solve %d: |p[%d]| beyond the grid's Nyquist wavenumber %g", i, j, kny);
+                emax2 += kny * kny;
+            } else {
+                emax2 += s.p[j] * s.p[j];
+            }
+        }
+        if (win->dt * std::sqrt(emax2) >= 2.8)
+            FAIL(SWF_E_ARG, "solve %d: dt * E_max = %g violates the RK4 stability bound 2.8", i, win->dt * std::sqrt(emax2));
+        P.solves.push_back(s);
+    }
+    // vertices
+    for (int v = 0; v < n_verts; ++v) {
+        const swf_vertex& V = verts[v];
+        if (V.u_solve < 0 || V.u_solve >= n_solves || V.v_solve < 0 || V.v_solve >= n_solves)
+            FAIL(SWF_E_ARG, "vertex %d: bad solve index", v);
+        const swf_solve &su = solves[V.u_solve], &sv = solves[V.v_solve];
+        if (su.kind != 0 || sv.kind != 1) FAIL(SWF_E_ARG, "vertex %d: needs a U solve and a V solve", v);
+        if (su.grid != sv.grid || su.field != sv.field) FAIL(SWF_E_ARG, "vertex %d: solves must share grid and field", v);
+        const double k0 = std::sqrt(V.k[0] * V.k[0] + V.k[1] * V.k[1] + V.k[2] * V.k[2]);
+        if (!(k0 > 0)) FAIL(SWF_E_ARG, "vertex %d: photon momentum must be non-zero", v);
+        const swf_grid& G = P.grids[su.grid];
+        for (int j = G.dim; j < 3; ++j)
+            if (std::fabs(su.p[j] + sv.p[j] - V.k[j]) > 1e-9 * (1.0 + std::fabs(V.k[j])))
+                FAIL(SWF_E_ARG, "vertex %d: p + q != k on trivial axis %d", v, j);
+        P.verts.push_back(V);
+    }
+
+    // ---- tables
+    auto add_r = [&](const std::vector<double>& v) { size_t o = P.rtab.size(); P.rtab.insert(P.rtab.end(), v.begin(), v.end()); return o; };
+    auto add_c = [&](const std::vector<cd>& v) { size_t o = P.ctab.size(); P.ctab.insert(P.ctab.end(), v.begin(), v.end()); return o; };
+    auto xcoord = [&](const swf_grid& G, int j, int i) { return j < G.dim ? -0.5 * G.L[j] + i * (G.L[j] / G.n[j]) : 0.0; };
+    // twiddles per length
+    std::vector<std::pair<int, size_t>> twoff;
+    auto tw_for = [&](int n) -> size_t {
+        for (auto& p : twoff) if (p.first == n) return p.second;
+        std::vector<cd> tw(n);
+        for (int m = 0; m < n; ++m) tw[m] = std::polar(1.0, -2.0 * PI * m / n);
+        size_t o = add_c(tw);
+        twoff.push_back({n, o});
+        return o;
+    };
+    // field tables per (grid, field)
+    std::vector<std::pair<std::pair<int, int>, int>> combos;   // (grid, field) -> first TermDev
+    for (int i = 0; i < n_solves; ++i) {
+        const swf_solve& s = P.solves[i];
+        const swf_grid& G = P.grids[s.grid];
+        int first = -1;
+        for (auto& c : combos) if (c.first.first == s.grid && c.first.second == s.field) first = c.second;
+        if (first < 0) {
+            first = (int)P.ht.size();
+            for (const auto& t : P.fields[s.field]) {
+                std::vector<double> tab;
+                for (int j = 0; j < 3; ++j)
+                    for (int k = 0; k < G.n[j]; ++k) tab.push_back(profile_h(t.fx[j], xcoord(G, j, k)));
+                TermDev d;
+                d.mu = t.mu;
+                d.ft_type = t.ft.type;
+                d.amp = t.amp;
+                d.c = t.ft.c;
+                d.w = t.ft.w;
+                d.k = t.ft.k;
+                d.phi = t.ft.phi;
+                d.tab = (long long)add_r(tab);
+                P.ht.push_back(d);
+            }
+            combos.push_back({{s.grid, s.field}, first});
+        }
+        SolveDev d;
+        memset(&d, 0, sizeof(d));
+        d.dim = G.dim;
+        d.nsites = 1;
+        for (int j = 0; j < 3; ++j) {
+            d.n[j] = G.n[j];
+            d.nsites *= G.n[j];
+            d.dk[j] = 2.0 * PI / G.L[j];
+        }
+        d.nrows = G.n[1] * G.n[2];
+        d.kind = s.kind;
+        const double sgn = s.kind == 0 ? 1.0 : -1.0;   // K = p for U, -p for V
+        for (int j = 0; j < 3; ++j) d.kap[j] = j >= G.dim ? sgn * s.p[j] : 0.0;
+        Spinor w = free_spinor(s.kind, s.spin, s.p);
+        for (int q = 0; q < 4; ++q) {
+            d.w[2 * q] = w.c[q].real();
+            d.w[2 * q + 1] = w.c[q].imag();
+        }
+        const double E = std::sqrt(1.0 + s.p[0] * s.p[0] + s.p[1] * s.p[1] + s.p[2] * s.p[2]);
+        d.E = sgn * E;
+        d.dV = 1.0;
+        for (int j = 0; j < G.dim; ++j) d.dV *= G.L[j] / G.n[j];
+        d.inv_n = 1.0 / (double)d.nsites;
+        d.term0 = first;
+        d.nterm = (int)P.fields[s.field].size();
+        std::vector<cd> ph;
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < G.n[j]; ++k) ph.push_back(j < G.dim ? std::polar(1.0, sgn * s.p[j] * xcoord(G, j, k)) : cd(1.0));
+        d.ph = (long long)add_c(ph);
+        d.mask = -1;
+        if (G.absorb_cells > 0) {
+            std::vector<double> m;
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < G.n[j]; ++k) {
+                    double v = 1.0;
+                    if (j < G.dim) {
+                        const int dd = std::min(k, G.n[j] - 1 - k);
+                        if (dd < G.absorb_cells) {
+                            const double sn = std::sin(0.5 * PI * (G.absorb_cells - dd) / G.absorb_cells);
+                            v = 1.0 - G.absorb_strength * sn * sn;
+                        }
+                    }
+                    m.push_back(v);
+                }
+            d.mask = (long long)add_r(m);
+        }
+        for (int j = 0; j < 3; ++j) d.tw[j] = (long long)tw_for(G.n[j] > 1 ? G.n[j] : G.n[0]);
+        P.hs.push_back(d);
+    }
+    for (int v = 0; v < n_verts; ++v) {
+        const swf_vertex& V = P.verts[v];
+        const swf_grid& G = P.grids[P.solves[V.u_solve].grid];
+        VertexDev d;
+        d.su = V.u_solve;
+        d.sv = V.v_solve;
+        d.k0 = std::sqrt(V.k[0] * V.k[0] + V.k[1] * V.k[1] + V.k[2] * V.k[2]);
+        for (int j = 0; j < 3; ++j) d.eps[j] = V.eps[j];
+        std::vector<cd> ph;
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < G.n[j]; ++k) ph.push_back(j < G.dim ? std::polar(1.0, V.k[j] * xcoord(G, j, k)) : cd(1.0));
+        d.phk = (long long)add_c(ph);
+        P.hv.push_back(d);
+    }
+    // ---- groups and work items
+    for (int g = 0; g < n_grids; ++g) {
+        Group gr;
+        gr.grid = g;
+        for (int i = 0; i < n_solves; ++i) if (P.solves[i].grid == g) gr.solves.push_back(i);
+        if (gr.solves.empty()) continue;
+        add_items(P, gr, P.fp64);
+        P.batched.push_back(gr);
+    }
+    for (int i = 0; i < n_solves; ++i) {
+        Group gr;
+        gr.grid = P.solves[i].grid;
+        gr.solves.push_back(i);
+        add_items(P, gr, P.fp64);
+        P.single.push_back(gr);
+    }
+    // ---- layout
+    size_t off = 0;
+    P.off_state = 0;
+    for (int i = 0; i < n_solves; ++i) {
+        P.solve_off.push_back(off);
+        off += 4 * align256(4 * (size_t)P.hs[i].nsites * P.csize);
+    }
+    P.state_bytes = off;
+    P.off_solves = off = align256(off);
+    off += sizeof(SolveDev) * n_solves;
+    P.off_terms = off = align256(off);
+    off += sizeof(TermDev) * std::max<size_t>(1, P.ht.size());
+    P.off_verts = off = align256(off);
+    off += sizeof(VertexDev) * std::max(1, n_verts);
+    P.off_rtab = off = align256(off);
+    off += P.rsize * std::max<size_t>(1, P.rtab.size());
+    P.off_ctab = off = align256(off);
+    off += P.csize * std::max<size_t>(1, P.ctab.size());
+    P.off_items = off = align256(off);
+    off += sizeof(int2) * std::max<size_t>(1, P.items.size());
+    P.off_step = off = align256(off);
+    off += 256;
+    P.off_M = off = align256(off);
+    off += sizeof(double2) * 3 * std::max(1, n_verts);
+    P.off_part = off = align256(off);
+    off += sizeof(double2) * 12 * (size_t)BW_BLOCKS * std::max(1, n_verts);
+    P.off_red = off = align256(off);
+    off += sizeof(double2) * 4 * (size_t)RED_BLOCKS;
+    P.total = align256(off);
+    return SWF_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ context
+struct PendingEv { hipEvent_t a, b; int kind; double bytes; };
+
+struct swf_ctx {
+    Plan P;
+    swf_options opt{};
+    hipStream_t user = nullptr, st = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    char* arena = nullptr;
+    bool own_arena = false;
+    int step = 0;
+    bool t_valid = true;
+    std::vector<char> kvalid;
+    std::vector<int> bw_done;
+    std::vector<cd> bw_cache;     // 3 terms finite + 3 past per vertex
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+    // profiling
+    std::vector<hipEvent_t> ev_free;
+    std::vector<PendingEv> pending;
+    long long st_launch[5] = {0, 0, 0, 0, 0};
+    double st_ms[5] = {0, 0, 0, 0, 0};
+    double st_bytes[5] = {0, 0, 0, 0, 0};
+
+    SolveDev* d_solves() { return (SolveDev*)(arena + P.off_solves); }
+    TermDev* d_terms() { return (TermDev*)(arena + P.off_terms); }
+    VertexDev* d_verts() { return (VertexDev*)(arena + P.off_verts); }
+    void* d_rtab() { return arena + P.off_rtab; }
+    void* d_ctab() { return arena + P.off_ctab; }
+    int2* d_items() { return (int2*)(arena + P.off_items); }
+    int* d_step() { return (int*)(arena + P.off_step); }
+    double2* d_M() { return (double2*)(arena + P.off_M); }
+    double2* d_part() { return (double2*)(arena + P.off_part); }
+    double2* d_red() { return (double2*)(arena + P.off_red); }
+    void* buf(int s, int role) { return arena + P.off_state + P.solve_off[s] + role * align256(4 * (size_t)P.hs[s].nsites * P.csize); }
+};
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);                     \
+            return SWF_E_HIP;                                                                 \
+        }                                                                                     \
+    } while (0)
+
+namespace {
+
+// Order the context's own stream after the caller's stream (on entry) and the
+// caller's stream after the context's work (on exit).
+static int enter(swf_ctx* ctx) {
+    HIPCHK(hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(hipStreamWaitEvent(ctx->st, ctx->ev_in, 0));
+    return SWF_OK;
+}
+static int leave(swf_ctx* ctx) {
+    HIPCHK(hipEventRecord(ctx->ev_out, ctx->st));
+    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+    return SWF_OK;
+}
+
+static int drain_profile(swf_ctx* ctx) {
+    for (auto& p : ctx->pending) {
+        HIPCHK(hipEventSynchronize(p.b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        ctx->st_launch[p.kind] += 1;
+        ctx->st_ms[p.kind] += ms;
+        ctx->st_bytes[p.kind] += p.bytes;
+        ctx->ev_free.push_back(p.a);
+        ctx->ev_free.push_back(p.b);
+    }
+    ctx->pending.clear();
+    return SWF_OK;
+}
+
+static int get_event(swf_ctx* ctx, hipEvent_t* e) {
+    if (ctx->ev_free.empty()) {
+        if ((int)ctx->pending.size() >= PROF_POOL) {
+            int r = drain_profile(ctx);
+            if (r) return r;
+        }
+    }
+    if (!ctx->ev_free.empty()) {
+        *e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return SWF_OK;
+    }
+    HIPCHK(hipEventCreate(e));
+    return SWF_OK;
+}
+
+static swf::PassArgs pass_args(swf_ctx* ctx) {
+    swf::PassArgs a;
+    memset(&a, 0, sizeof(a));
+    a.solves = ctx->d_solves();
+    a.terms = ctx->d_terms();
+    a.rtab = ctx->d_rtab();
+    a.ctab = ctx->d_ctab();
+    a.step = ctx->d_step();
+    a.t_out = ctx->P.win.t_out;
+    a.dt = ctx->P.win.dt;
+    return a;
+}
+
+static double group_sites(swf_ctx* ctx, const Group& g) {
+    double s = 0;
+    for (int i : g.solves) s += (double)ctx->P.hs[i].nsites;
+    return s;
+}
+
+// Launch one pass kernel over n items starting at item offset `it`.
+static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threads, size_t lds, swf::PassArgs a,
+                  int kind, double bytes) {
+    if (nitems <= 0) return SWF_OK;
+    a.items = ctx->d_items() + it;
+    void* args[] = {&a};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = ctx->opt.profile && !ctx->gexec;
+    if (prof) {
+        int r = get_event(ctx, &e0);
+        if (!r) r = get_event(ctx, &e1);
+        if (r) return r;
+        HIPCHK(hipEventRecord(e0, ctx->st));
+    }
+    HIPCHK(hipLaunchKernel(fn, dim3(nitems), dim3(threads), args, lds, ctx->st));
+    if (prof) {
+        HIPCHK(hipEventRecord(e1, ctx->st));
+        ctx->pending.push_back({e0, e1, kind, bytes});
+    }
+    return SWF_OK;
+}
+
+// x-axis pass of a group in the given mode.
+static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, int dst, double tex, long long ph2) {
+    const auto* k = g.k[0];
+    swf::PassArgs a = pass_args(ctx);
+    a.stage = stage;
+    a.src = src;
+    a.dst = dst;
+    a.t_explicit = tex;
+    a.ph2 = ph2;
+    a.h0row = ctx->P.grids[g.grid].dim == 1 ? 1 : 0;
+    double trav = 2;
+    if (mode == swf::ROW_STAGE) trav = (stage == 0 || stage == 3) ? 5 : 7;
+    else if (mode == swf::ROW_RHS) trav = 3;
+    return launch(ctx, k->row[mode], g.n_row, g.it_row, k->row_threads, k->row_lds, a, 0,
+                  trav * 4.0 * ctx->P.csize * group_sites(ctx, g));
+}
+
+static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role) {
+    const auto* k = g.k[axis];
+    swf::PassArgs a = pass_args(ctx);
+    a.dst = role;
+    a.src = role;
+    const int n = axis == 1 ? g.n_coly : g.n_colz;
+    const size_t it = axis == 1 ? g.it_coly : g.it_colz;
+    return launch(ctx, k->col[axis - 1][mode], n, it, k->col_threads, k->col_lds, a, axis,
+                  2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g));
+}
+
+// k-space kinetic pass of a group (between the forward x pass and the row epilogue).
+static int kinetic_cols(swf_ctx* ctx, const Group& g, int role) {
+    const int dim = ctx->P.grids[g.grid].dim;
+    int r = SWF_OK;
+    if (dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, role);
+    if (dim == 3) {
+        r = col_pass(ctx, g, 1, swf::COL_FWD, role);
+        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, role);
+        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, role);
+    }
+    return r;
+}
+
+static const std::vector<Group>& groups(swf_ctx* ctx) { return ctx->opt.batched ? ctx->P.batched : ctx->P.single; }
+
+static int bw_stage(swf_ctx* ctx, int stage) {
+    if (ctx->P.hv.empty()) return SWF_OK;
+    swf::BwArgs b;
+    memset(&b, 0, sizeof(b));
+    b.solves = ctx->d_solves();
+    b.verts = ctx->d_verts();
+    b.ctab = ctx->d_ctab();
+    b.step = ctx->d_step();
+    b.t_out = ctx->P.win.t_out;
+    b.dt = ctx->P.win.dt;
+    b.stage = stage;
+    b.nvert = (int)ctx->P.hv.size();
+    b.part = ctx->d_part();
+    b.M = ctx->d_M();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = ctx->opt.profile && !ctx->gexec;
+    if (prof) {
+        int r = get_event(ctx, &e0);
+        if (!r) r = get_event(ctx, &e1);
+        if (r) return r;
+        HIPCHK(hipEventRecord(e0, ctx->st));
+    }
+    HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, ctx->st));
+    if (prof) {
+        double bytes = 0;
+        for (auto& v : ctx->P.hv) bytes += 2.0 * 4.0 * ctx->P.csize * (double)ctx->P.hs[v.su].nsites;
+        HIPCHK(hipEventRecord(e1, ctx->st));
+        ctx->pending.push_back({e0, e1, 3, bytes});
+    }
+    return SWF_OK;
+}
+
+static int bw_accum(swf_ctx* ctx) {
+    if (ctx->P.hv.empty()) return SWF_OK;
+    swf::BwArgs b;
+    memset(&b, 0, sizeof(b));
+    b.solves = ctx->d_solves();
+    b.verts = ctx->d_verts();
+    b.dt = ctx->P.win.dt;
+    b.nvert = (int)ctx->P.hv.size();
+    b.part = ctx->d_part();
+    b.M = ctx->d_M();
+    HIPCHK(swf::launch_bw_accum(b, BW_BLOCKS, ctx->st));
+    return SWF_OK;
+}
+
+// Forward x pass Y -> T for every solve (after the state was set from the host).
+static int refresh_T(swf_ctx* ctx) {
+    if (ctx->t_valid) return SWF_OK;
+    for (const auto& g : groups(ctx)) {
+        int r = row_pass(ctx, g, swf::ROW_FWD, 0, swf::BUF_Y, swf::BUF_T, 0, 0);
+        if (r) return r;
+    }
+    ctx->t_valid = true;
+    return SWF_OK;
+}
+
+// Enqueue one full RK4 step of every solve.
+static int enqueue_step(swf_ctx* ctx) {
+    for (int s = 0; s < 4; ++s) {
+        int r = bw_stage(ctx, s);
+        if (r) return r;
+        for (const auto& g : groups(ctx)) {
+            r = kinetic_cols(ctx, g, swf::BUF_T);
+            if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0);
+            if (r) return r;
+        }
+    }
+    int r = bw_accum(ctx);
+    if (r) return r;
+    HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
+    return SWF_OK;
+}
+
+static int build_graph(swf_ctx* ctx) {
+    HIPCHK(hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal));
+    int r = enqueue_step(ctx);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->st, &g);
+    if (r) return r;
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+        return SWF_E_HIP;
+    }
+    ctx->graph = g;
+    HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    return SWF_OK;
+}
+
+// Host sum of per-block partials (fixed order).
+static int reduce(swf_ctx* ctx, int kind, swf::RedArgs a, int nv, std::vector<cd>& out) {
+    a.solves = ctx->d_solves();
+    a.out = ctx->d_red();
+    HIPCHK(swf::launch_reduction(ctx->P.fp64, kind, a, RED_BLOCKS, ctx->st));
+    std::vector<double2> h((size_t)RED_BLOCKS * nv);
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->d_red(), h.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    out.assign(nv, cd(0));
+    for (int b = 0; b < RED_BLOCKS; ++b)
+        for (int v = 0; v < nv; ++v) out[v] += cd(h[(size_t)b * nv + v].x, h[(size_t)b * nv + v].y);
+    return SWF_OK;
+}
+
+static void lattice_x(swf_ctx* ctx, int s, swf::RedArgs& a) {
+    const swf_grid& G = ctx->P.grids[ctx->P.solves[s].grid];
+    for (int j = 0; j < 3; ++j) {
+        a.x0[j] = j < G.dim ? -0.5 * G.L[j] : 0.0;
+        a.dx[j] = j < G.dim ? G.L[j] / G.n[j] : 0.0;
+    }
+}
+
+// Full forward transform of psi_s of solve s into its T buffer.
+static int kspace(swf_ctx* ctx, int s) {
+    if (ctx->kvalid[s]) return SWF_OK;
+    const Group& g = ctx->P.single[s];
+    const int dim = ctx->P.grids[g.grid].dim;
+    int r = row_pass(ctx, g, swf::ROW_FWD, 0, swf::BUF_Y, swf::BUF_T, 0, 0);
+    if (!r && dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_T);
+    if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_T);
+    if (r) return r;
+    ctx->kvalid[s] = 1;
+    ctx->t_valid = false;
+    return SWF_OK;
+}
+
+// F_q = dV sum_x psi_q(x) exp(-i kappa.x) of solve s's Y buffer.
+static int fourier_coeff(swf_ctx* ctx, int s, const double* kappa, Spinor& F) {
+    swf::RedArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sa = s;
+    a.ra = swf::BUF_Y;
+    for (int j = 0; j < 3; ++j) a.kv[j] = kappa[j];
+    lattice_x(ctx, s, a);
+    std::vector<cd> o;
+    int r = reduce(ctx, swf::RED_XFOURIER, a, 4, o);
+    if (r) return r;
+    for (int q = 0; q < 4; ++q) F.c[q] = o[q] * ctx->P.hs[s].dV;
+    return SWF_OK;
+}
+
+static Spinor solve_spinor(swf_ctx* ctx, int s) {
+    Spinor w;
+    for (int q = 0; q < 4; ++q) w.c[q] = cd(ctx->P.hs[s].w[2 * q], ctx->P.hs[s].w[2 * q + 1]);
+    return w;
+}
+
+static int projected(swf_ctx* ctx, int sa, int sb, int sign, cd& out) {
+    int r = kspace(ctx, sa);
+    if (!r && sb != sa) r = kspace(ctx, sb);
+    if (r) return r;
+    swf::RedArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sa = sa;
+    a.sb = sb;
+    a.ra = a.rb = swf::BUF_T;
+    a.sign = sign;
+    std::vector<cd> o;
+    r = reduce(ctx, swf::RED_KPROJ, a, 1, o);
+    if (r) return r;
+    out = o[0] * ctx->P.hs[sa].dV * ctx->P.hs[sa].inv_n;
+    return SWF_OK;
+}
+
+static int check_pair(swf_ctx* ctx, int i, int j) {
+    const auto& P = ctx->P;
+    if (i < 0 || j < 0 || i >= (int)P.solves.size() || j >= (int)P.solves.size()) {
+        ctx->err = "bad solve index";
+        return SWF_E_ARG;
+    }
+    if (P.solves[i].kind != 0 || P.solves[j].kind != 1) {
+        ctx->err = "pair amplitude needs a U solve (i) and a V solve (j)";
+        return SWF_E_ARG;
+    }
+    if (P.solves[i].grid != P.solves[j].grid) {
+        ctx->err = "pair amplitude needs both solves on one grid";
+        return SWF_E_ARG;
+    }
+    for (int a = P.grids[P.solves[i].grid].dim; a < 3; ++a)
+        if (std::fabs(P.solves[i].p[a] + P.solves[j].p[a]) > 1e-12) {
+            ctx->err = "pair amplitude needs q_perp = -p_perp on trivial axes";
+            return SWF_E_ARG;
+        }
+    return SWF_OK;
+}
+
+static int pair_amp(swf_ctx* ctx, int i, int j, int form, cd& out) {
+    int r = check_pair(ctx, i, j);
+    if (r) return r;
+    const double tin = ctx->P.win.t_in;
+    const auto& HU = ctx->P.hs[i];
+    const auto& HV = ctx->P.hs[j];
+    cd proj_term;
+    r = projected(ctx, i, j, form == 1 ? +1 : -1, proj_term);
+    if (r) return r;
+    const swf_solve& su = ctx->P.solves[i];
+    const swf_solve& sv = ctx->P.solves[j];
+    cd direct;
+    if (form == 1) {
+        // (U_b|V_s) = dV e^{i E_U t} sum_q conj(u_q) F_V,q(p)
+        Spinor F;
+        r = fourier_coeff(ctx, j, su.p, F);
+        if (r) return r;
+        direct = std::polar(1.0, HU.E * tin) * dot(solve_spinor(ctx, i), F);
+    } else {
+        // (U_s|V_b) = dV e^{-i E_V t} sum_q v_q conj(F_U,q(-q))
+        double kap[3] = {-sv.p[0], -sv.p[1], -sv.p[2]};
+        Spinor F;
+        r = fourier_coeff(ctx, i, kap, F);
+        if (r) return r;
+        direct = std::polar(1.0, -HV.E * tin) * dot(F, solve_spinor(ctx, j));
+    }
+    out = direct + proj_term;
+    return SWF_OK;
+}
+
+// Breit-Wheeler amplitude terms of vertex v at t_in.
+static int bw_terms(swf_ctx* ctx, int v) {
+    if (ctx->bw_done[v]) return SWF_OK;
+    const VertexDev& V = ctx->P.hv[v];
+    const swf_vertex& VX = ctx->P.verts[v];
+    const int su = V.su, sv = V.sv;
+    const double tin = ctx->P.win.t_in;
+    // finite parts: M(t_in) accumulated from t_out, M_finite = -M(t_in)
+    double2 M[3];
+    HIPCHK(hipMemcpyAsync(M, ctx->d_M() + 3 * v, sizeof(M), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    for (int t = 0; t < 3; ++t) ctx->bw_cache[6 * v + t] = -cd(M[t].x, M[t].y);
+    // (scat, scat) past term: FFT(U_s) and FFT(V_s e^{i k.x})
+    int r = kspace(ctx, su);
+    if (r) return r;
+    {
+        const Group& g = ctx->P.single[sv];
+        const int dim = ctx->P.grids[g.grid].dim;
+        r = row_pass(ctx, g, swf::ROW_FWDPH, 0, swf::BUF_Y, swf::BUF_ACC, 0, V.phk);
+        if (!r && dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_ACC);
+        if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_ACC);
+        if (r) return r;
+        ctx->t_valid = false;
+    }
+    swf::RedArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sa = su;
+    a.sb = sv;
+    a.ra = swf::BUF_T;
+    a.rb = swf::BUF_ACC;
+    for (int j = 0; j < 3; ++j) {
+        a.kv[j] = VX.k[j];
+        a.eps[j] = VX.eps[j];
+    }
+    a.k0 = V.k0;
+    std::vector<cd> o;
+    r = reduce(ctx, swf::RED_KBWPAST, a, 1, o);
+    if (r) return r;
+    const auto& HU = ctx->P.hs[su];
+    ctx->bw_cache[6 * v + 3] = std::polar(1.0, -V.k0 * tin) * o[0] * HU.dV * HU.inv_n;
+    const swf_solve& SU = ctx->P.solves[su];
+    const swf_solve& SV = ctx->P.solves[sv];
+    const double* eps = VX.eps;
+    // (back, scat): kappa = p - k
+    {
+        double kap[3];
+        for (int j = 0; j < 3; ++j) kap[j] = SU.p[j] - VX.k[j];
+        Spinor Vc;
+        r = fourier_coeff(ctx, sv, kap, Vc);
+        if (r) return r;
+        const double p0 = std::sqrt(1.0 + SU.p[0] * SU.p[0] + SU.p[1] * SU.p[1] + SU.p[2] * SU.p[2]);
+        const double Ek = std::sqrt(1.0 + kap[0] * kap[0] + kap[1] * kap[1] + kap[2] * kap[2]);
+        const Spinor u = solve_spinor(ctx, su);
+        cd m = 0;
+        for (int sp = -1; sp <= 1; sp += 2) {
+            const Spinor PV = proj(Vc, kap, sp);
+            m += dot(u, gamma_eps(PV, eps)) / cd(0.0, p0 - sp * Ek - V.k0);
+        }
+        ctx->bw_cache[6 * v + 4] = m * std::polar(1.0, (p0 - V.k0) * tin);
+    }
+    // (scat, back): kappa = k - q
+    {
+        double kap[3];
+        for (int j = 0; j < 3; ++j) kap[j] = VX.k[j] - SV.p[j];
+        Spinor Uc;
+        r = fourier_coeff(ctx, su, kap, Uc);
+        if (r) return r;
+        const double q0 = std::sqrt(1.0 + SV.p[0] * SV.p[0] + SV.p[1] * SV.p[1] + SV.p[2] * SV.p[2]);
+        const double Ek = std::sqrt(1.0 + kap[0] * kap[0] + kap[1] * kap[1] + kap[2] * kap[2]);
+        const Spinor vsp = solve_spinor(ctx, sv);
+        const Spinor gv = gamma_eps(vsp, eps);
+        cd m = 0;
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const Spinor PU = proj(Uc, kap, sg);
+            m += dot(PU, gv) / cd(0.0, sg * Ek + q0 - V.k0);
+        }
+        ctx->bw_cache[6 * v + 5] = m * std::polar(1.0, (q0 - V.k0) * tin);
+    }
+    ctx->bw_done[v] = 1;
+    return SWF_OK;
+}
+
+static swf_ctx* g_dummy = nullptr;
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+int swf_supported_n(int n) { return supported_n(n) ? 1 : 0; }
+
+swf_status swf_workspace_size(const swf_grid* grids, int n_grids, const swf_term* terms, const int* ffirst,
+                              int n_fields, const swf_solve* solves, int n_solves, const swf_vertex* vertices,
+                              int n_vertices, const swf_window* window, const swf_options* opt, size_t* bytes) {
+    Plan P;
+    std::string err;
+    int r = build_plan(P, err, grids, n_grids, terms, ffirst, n_fields, solves, n_solves, vertices, n_vertices, window, opt);
+    if (r) {
+        g_init_error = err;
+        return (swf_status)r;
+    }
+    if (bytes) *bytes = P.total;
+    return SWF_OK;
+}
+
+swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, const int* ffirst, int n_fields,
+                    const swf_solve* solves, int n_solves, const swf_vertex* vertices, int n_vertices,
+                    const swf_window* window, const swf_options* opt, swf_ctx** out) {
+    if (out) *out = nullptr;
+    if (!out) {
+        g_init_error = "out is NULL";
+        return SWF_E_ARG;
+    }
+    swf_ctx* ctx = new swf_ctx();
+    std::string err;
+    int r = build_plan(ctx->P, err, grids, n_grids, terms, ffirst, n_fields, solves, n_solves, vertices, n_vertices, window, opt);
+    if (r) {
+        g_init_error = err;
+        delete ctx;
+        return (swf_status)r;
+    }
+    ctx->opt = *opt;
+    ctx->opt.tune_cache = nullptr;
+    ctx->user = (hipStream_t)opt->stream;
+    auto fail = [&](int code) {
+        g_init_error = ctx->err;
+        swf_free(ctx);
+        return (swf_status)code;
+    };
+#define INITCHK(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess) {                                                         \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);               \
+            return fail(SWF_E_HIP);                                                     \
+        }                                                                               \
+    } while (0)
+    INITCHK(hipStreamCreateWithFlags(&ctx->st, hipStreamNonBlocking));
+    INITCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    INITCHK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    Plan& P = ctx->P;
+    if (opt->workspace) {
+        if (opt->workspace_bytes < P.total) {
+            char b[256];
+            snprintf(b, sizeof(b), "workspace of %zu bytes is smaller than the %zu needed", opt->workspace_bytes, P.total);
+            ctx->err = b;
+            return fail(SWF_E_NOMEM);
+        }
+        if (((uintptr_t)opt->workspace) & 255) {
+            ctx->err = "workspace must be 256-byte aligned";
+            return fail(SWF_E_ARG);
+        }
+        ctx->arena = (char*)opt->workspace;
+    } else {
+        hipError_t e = hipMalloc((void**)&ctx->arena, P.total);
+        if (e != hipSuccess) {
+            ctx->arena = nullptr;
+            ctx->err = std::string("hipMalloc of the arena failed: ") + hipGetErrorString(e);
+            return fail(SWF_E_NOMEM);
+        }
+        ctx->own_arena = true;
+    }
+    // fill buffer pointers and upload descriptors / tables
+    for (size_t i = 0; i < P.hs.size(); ++i)
+        for (int role = 0; role < 4; ++role) P.hs[i].buf[role] = ctx->buf((int)i, role);
+    INITCHK(hipMemsetAsync(ctx->arena + P.off_state, 0, P.state_bytes, ctx->st));
+    INITCHK(hipMemcpyAsync(ctx->d_solves(), P.hs.data(), sizeof(SolveDev) * P.hs.size(), hipMemcpyHostToDevice, ctx->st));
+    if (!P.ht.empty())
+        INITCHK(hipMemcpyAsync(ctx->d_terms(), P.ht.data(), sizeof(TermDev) * P.ht.size(), hipMemcpyHostToDevice, ctx->st));
+    if (!P.hv.empty())
+        INITCHK(hipMemcpyAsync(ctx->d_verts(), P.hv.data(), sizeof(VertexDev) * P.hv.size(), hipMemcpyHostToDevice, ctx->st));
+    std::vector<char> rt(P.rsize * std::max<size_t>(1, P.rtab.size())), ct(P.csize * std::max<size_t>(1, P.ctab.size()));
+    for (size_t i = 0; i < P.rtab.size(); ++i) {
+        if (P.fp64) ((double*)rt.data())[i] = P.rtab[i];
+        else ((float*)rt.data())[i] = (float)P.rtab[i];
+    }
+    for (size_t i = 0; i < P.ctab.size(); ++i) {
+        if (P.fp64) {
+            ((double*)ct.data())[2 * i] = P.ctab[i].real();
+            ((double*)ct.data())[2 * i + 1] = P.ctab[i].imag();
+        } else {
+            ((float*)ct.data())[2 * i] = (float)P.ctab[i].real();
+            ((float*)ct.data())[2 * i + 1] = (float)P.ctab[i].imag();
+        }
+    }
+    INITCHK(hipMemcpyAsync(ctx->d_rtab(), rt.data(), rt.size(), hipMemcpyHostToDevice, ctx->st));
+    INITCHK(hipMemcpyAsync(ctx->d_ctab(), ct.data(), ct.size(), hipMemcpyHostToDevice, ctx->st));
+    INITCHK(hipMemcpyAsync(ctx->d_items(), P.items.data(), sizeof(int2) * P.items.size(), hipMemcpyHostToDevice, ctx->st));
+    INITCHK(hipMemsetAsync(ctx->d_step(), 0, 256, ctx->st));
+    INITCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, P.hv.size()), ctx->st));
+    INITCHK(hipStreamSynchronize(ctx->st));
+    // allow the dynamic LDS every pass kernel of these sizes asks for
+    for (const auto* gl : {&P.batched, &P.single})
+        for (const auto& g : *gl)
+            for (int ax = 0; ax < 3; ++ax) {
+                const auto* k = g.k[ax];
+                if (!k) continue;
+                for (int m = 0; m < 5; ++m)
+                    INITCHK(hipFuncSetAttribute(k->row[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row_lds));
+                for (int a = 0; a < 2; ++a)
+                    for (int m = 0; m < 3; ++m)
+                        INITCHK(hipFuncSetAttribute(k->col[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col_lds));
+            }
+    ctx->kvalid.assign(P.solves.size(), 0);
+    ctx->bw_done.assign(P.hv.size(), 0);
+    ctx->bw_cache.assign(6 * P.hv.size(), cd(0));
+    if (opt->use_graph && !opt->profile) {
+        int rr = build_graph(ctx);
+        if (rr) return fail(rr);
+    }
+    *out = ctx;
+    return SWF_OK;
+#undef INITCHK
+}
+
+swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
+    if (!ctx) return SWF_E_ARG;
+    if (n_steps < 0) {
+        ctx->err = "n_steps must be >= 0";
+        return SWF_E_ARG;
+    }
+    if (ctx->step + n_steps > ctx->P.steps) {
+        ctx->err = "swf_step past t_in";
+        return SWF_E_ORDER;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    r = refresh_T(ctx);
+    if (r) return (swf_status)r;
+    for (int i = 0; i < n_steps; ++i) {
+        if (ctx->gexec) {
+            HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
+        } else {
+            r = enqueue_step(ctx);
+            if (r) return (swf_status)r;
+        }
+    }
+    if (n_steps > 0) {
+        ctx->step += n_steps;
+        std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
+        std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
+    }
+    r = leave(ctx);
+    if (r) return (swf_status)r;
+    if (steps_left) *steps_left = ctx->P.steps - ctx->step;
+    return SWF_OK;
+}
+
+swf_status swf_sync(swf_ctx* ctx) {
+    if (!ctx) return SWF_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    int r = drain_profile(ctx);
+    return (swf_status)r;
+}
+
+swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]) {
+    if (!ctx || !out) return SWF_E_ARG;
+    if (ctx->step != ctx->P.steps) {
+        ctx->err = "amplitudes are defined at t_in: step to the end first";
+        return SWF_E_ORDER;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    cd val;
+    if (which == SWF_AMP_PAIR1 || which == SWF_AMP_PAIR2) {
+        r = pair_amp(ctx, i, j, which == SWF_AMP_PAIR1 ? 1 : 2, val);
+    } else if (which == SWF_AMP_BW) {
+        if (i < 0 || i >= (int)ctx->P.hv.size() || j < -1 || j > 2) {
+            ctx->err = "bad vertex or term index";
+            return SWF_E_ARG;
+        }
+        r = bw_terms(ctx, i);
+        if (!r) {
+            if (j < 0) {
+                val = 0;
+                for (int t = 0; t < 6; ++t) val += ctx->bw_cache[6 * i + t];
+            } else {
+                val = ctx->bw_cache[6 * i + j] + ctx->bw_cache[6 * i + 3 + j];
+            }
+        }
+    } else {
+        ctx->err = "unknown amplitude kind";
+        return SWF_E_ARG;
+    }
+    if (r) return (swf_status)r;
+    r = leave(ctx);
+    if (r) return (swf_status)r;
+    out[0] = val.real();
+    out[1] = val.imag();
+    return std::isfinite(out[0]) && std::isfinite(out[1]) ? SWF_OK : SWF_E_NONFINITE;
+}
+
+swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out) {
+    if (!ctx || !out) return SWF_E_ARG;
+    if (ctx->step != ctx->P.steps) {
+        ctx->err = "probabilities are defined at t_in: step to the end first";
+        return SWF_E_ORDER;
+    }
+    if (which == SWF_P_MARGINAL_E || which == SWF_P_MARGINAL_POS) {
+        if (i < 0 || i >= (int)ctx->P.solves.size()) {
+            ctx->err = "bad solve index";
+            return SWF_E_ARG;
+        }
+        const int want = which == SWF_P_MARGINAL_E ? 0 : 1;
+        if (ctx->P.solves[i].kind != want) {
+            ctx->err = which == SWF_P_MARGINAL_E ? "electron marginal needs a U solve" : "positron marginal needs a V solve";
+            return SWF_E_ARG;
+        }
+        int r = enter(ctx);
+        if (r) return (swf_status)r;
+        cd v;
+        r = projected(ctx, i, i, want == 0 ? -1 : +1, v);
+        if (r) return (swf_status)r;
+        r = leave(ctx);
+        if (r) return (swf_status)r;
+        *out = v.real();
+    } else if (which == SWF_P_PAIR || which == SWF_P_BW) {
+        double a[2];
+        swf_status r = swf_amplitude(ctx, which == SWF_P_PAIR ? SWF_AMP_PAIR1 : SWF_AMP_BW, i, which == SWF_P_PAIR ? j : -1, a);
+        if (r) return r;
+        *out = a[0] * a[0] + a[1] * a[1];
+    } else {
+        ctx->err = "unknown probability kind";
+        return SWF_E_ARG;
+    }
+    return std::isfinite(*out) ? SWF_OK : SWF_E_NONFINITE;
+}
+
+swf_status swf_diagnostics(swf_ctx* ctx, int i, double out[4]) {
+    if (!ctx || !out) return SWF_E_ARG;
+    if (i < 0 || i >= (int)ctx->P.solves.size()) {
+        ctx->err = "bad solve index";
+        return SWF_E_ARG;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    swf::RedArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sa = i;
+    a.ra = swf::BUF_Y;
+    const swf_solve& s = ctx->P.solves[i];
+    const double sgn = s.kind == 0 ? 1.0 : -1.0;
+    for (int j = 0; j < 3; ++j) a.kv[j] = sgn * s.p[j];
+    a.t = ctx->P.win.t_out - (double)ctx->step * ctx->P.win.dt;
+    lattice_x(ctx, i, a);
+    a.solves = ctx->d_solves();
+    a.out = ctx->d_red();
+    HIPCHK(swf::launch_reduction(ctx->P.fp64, swf::RED_XDIAG, a, RED_BLOCKS, ctx->st));
+    std::vector<double2> h((size_t)RED_BLOCKS * 3);
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->d_red(), h.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    double ss = 0, mx = 0, bad = 0;
+    cd bs = 0;
+    for (int b = 0; b < RED_BLOCKS; ++b) {
+        ss += h[3 * b].x;
+        bs += cd(h[3 * b + 1].x, h[3 * b + 1].y);
+        mx = std::max(mx, h[3 * b + 2].x);
+        bad += h[3 * b + 2].y;
+    }
+    const double dV = ctx->P.hs[i].dV;
+    out[0] = ss * dV;
+    out[1] = 2.0 * (bs * dV).real();
+    out[2] = mx;
+    out[3] = bad == 0 ? 1.0 : 0.0;
+    r = leave(ctx);
+    if (r) return (swf_status)r;
+    if (bad != 0) {
+        ctx->err = "non-finite values in the state";
+        return SWF_E_NONFINITE;
+    }
+    return SWF_OK;
+}
+
+static swf_status copy_state(swf_ctx* ctx, int i, int role, double* host, bool to_host) {
+    const size_t n = 4 * (size_t)ctx->P.hs[i].nsites;
+    void* d = ctx->buf(i, role);
+    if (ctx->P.fp64) {
+        if (to_host) HIPCHK(hipMemcpyAsync(host, d, n * 16, hipMemcpyDeviceToHost, ctx->st));
+        else HIPCHK(hipMemcpyAsync(d, host, n * 16, hipMemcpyHostToDevice, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    } else {
+        std::vector<float> tmp(2 * n);
+        if (to_host) {
+            HIPCHK(hipMemcpyAsync(tmp.data(), d, n * 8, hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            for (size_t k = 0; k < 2 * n; ++k) host[k] = tmp[k];
+        } else {
+            for (size_t k = 0; k < 2 * n; ++k) tmp[k] = (float)host[k];
+            HIPCHK(hipMemcpyAsync(d, tmp.data(), n * 8, hipMemcpyHostToDevice, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+        }
+    }
+    return SWF_OK;
+}
+
+swf_status swf_get_psi(swf_ctx* ctx, int i, double* host) {
+    if (!ctx || !host || i < 0 || i >= (int)ctx->P.solves.size()) return SWF_E_ARG;
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    return copy_state(ctx, i, swf::BUF_Y, host, true);
+}
+
+swf_status swf_set_psi(swf_ctx* ctx, int i, const double* host, int step_index) {
+    if (!ctx || !host || i < 0 || i >= (int)ctx->P.solves.size()) return SWF_E_ARG;
+    if (step_index < 0 || step_index > ctx->P.steps) {
+        ctx->err = "step_index out of range";
+        return SWF_E_ARG;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    swf_status s = copy_state(ctx, i, swf::BUF_Y, const_cast<double*>(host), false);
+    if (s) return s;
+    ctx->step = step_index;
+    HIPCHK(hipMemcpyAsync(ctx->d_step(), &step_index, sizeof(int), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    ctx->t_valid = false;
+    std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
+    std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
+    return SWF_OK;
+}
+
+swf_status swf_get_bw_state(swf_ctx* ctx, int i, double out[6]) {
+    if (!ctx || !out || i < 0 || i >= (int)ctx->P.hv.size()) return SWF_E_ARG;
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    HIPCHK(hipMemcpyAsync(out, ctx->d_M() + 3 * i, 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return SWF_OK;
+}
+
+swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]) {
+    if (!ctx || !in || i < 0 || i >= (int)ctx->P.hv.size()) return SWF_E_ARG;
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    HIPCHK(hipMemcpyAsync(ctx->d_M() + 3 * i, in, 6 * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    ctx->bw_done[i] = 0;
+    return SWF_OK;
+}
+
+swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in, double* out) {
+    if (!ctx || !in || !out || i < 0 || i >= (int)ctx->P.solves.size() || op < 0 || op > 2) return SWF_E_ARG;
+    if (ctx->step != 0 && ctx->step != ctx->P.steps) {
+        ctx->err = "swf_apply_op is only valid before stepping or at t_in";
+        return SWF_E_ORDER;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    swf_status s = copy_state(ctx, i, swf::BUF_YS, const_cast<double*>(in), false);
+    if (s) return s;
+    const Group& g = ctx->P.single[i];
+    const int dim = ctx->P.grids[g.grid].dim;
+    r = row_pass(ctx, g, swf::ROW_FWD, 0, swf::BUF_YS, swf::BUF_T, 0, 0);
+    if (r) return (swf_status)r;
+    int role_out = swf::BUF_T;
+    if (op == 0) {
+        if (dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_T);
+        if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_T);
+    } else {
+        r = kinetic_cols(ctx, g, swf::BUF_T);
+        if (!r) r = row_pass(ctx, g, op == 1 ? swf::ROW_INV : swf::ROW_RHS, 0, swf::BUF_YS, swf::BUF_ACC, t, 0);
+        role_out = swf::BUF_ACC;
+    }
+    if (r) return (swf_status)r;
+    ctx->t_valid = false;
+    ctx->kvalid[i] = 0;
+    std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
+    return copy_state(ctx, i, role_out, out, true);
+}
+
+swf_status swf_kernel_stats(swf_ctx* ctx, int kind, long long* launches, double* ms, double* bytes) {
+    if (!ctx || kind < 0 || kind > 4) return SWF_E_ARG;
+    int r = drain_profile(ctx);
+    if (r) return (swf_status)r;
+    if (launches) *launches = ctx->st_launch[kind];
+    if (ms) *ms = ctx->st_ms[kind];
+    if (bytes) *bytes = ctx->st_bytes[kind];
+    return SWF_OK;
+}
+
+swf_status swf_reset_stats(swf_ctx* ctx) {
+    if (!ctx) return SWF_E_ARG;
+    int r = drain_profile(ctx);
+    if (r) return (swf_status)r;
+    for (int k = 0; k < 5; ++k) {
+        ctx->st_launch[k] = 0;
+        ctx->st_ms[k] = 0;
+        ctx->st_bytes[k] = 0;
+    }
+    return SWF_OK;
+}
+
+swf_status swf_steps(swf_ctx* ctx, int* total, int* done) {
+    if (!ctx) return SWF_E_ARG;
+    if (total) *total = ctx->P.steps;
+    if (done) *done = ctx->step;
+    return SWF_OK;
+}
+
+const char* swf_last_error(const swf_ctx* ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+void swf_free(swf_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->st) hipStreamSynchronize(ctx->st);
+    for (auto& p : ctx->pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->ev_free) hipEventDestroy(e);
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    if (ctx->own_arena && ctx->arena) hipFree(ctx->arena);
+    if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) hipEventDestroy(ctx->ev_out);
+    if (ctx->st) hipStreamDestroy(ctx->st);
+    (void)g_dummy;
+    delete ctx;
+}
+
+}  // extern "C"

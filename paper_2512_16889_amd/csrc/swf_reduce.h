@@ -1,0 +1,52 @@
+// Host/device interface of the reduction kernels and the per-size kernel tables.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "swf_dev.h"
+
+namespace swf {
+
+enum { RED_KPROJ = 0, RED_KBWPAST = 1, RED_XFOURIER = 2, RED_XDIAG = 3 };
+
+struct RedArgs {
+    const SolveDev* solves;
+    int sa, sb;          // solves
+    int ra, rb;          // buffer roles
+    int sign;            // projector sign (RED_KPROJ)
+    double kv[3];        // photon momentum (RED_KBWPAST), kappa (RED_XFOURIER), K (RED_XDIAG)
+    double k0;           // photon energy
+    double eps[3];       // polarisation
+    double t;            // time (RED_XDIAG)
+    double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
+    double2* out;        // per-block partials
+};
+
+struct VertexDev {
+    int su, sv;
+    double k0;
+    double eps[3];
+    long long phk;       // complex offset of exp(i k_j x_j) tables (n0 + n1 + n2 entries)
+};
+
+struct BwArgs {
+    const SolveDev* solves;
+    const VertexDev* verts;
+    const void* ctab;
+    const int* step;
+    double t_out, dt;
+    int stage;
+    int nvert;
+    double2* part;       // [vertex][stage][block][3]
+    double2* M;          // [vertex][3] accumulated integrals (device, double)
+};
+
+hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
+hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st);
+hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
+hipError_t launch_tick(int* step, hipStream_t st);
+
+struct SizeKernels;
+// Kernel table of an FFT length for single (fp64 = 0) or double precision, NULL if unsupported.
+const SizeKernels* size_kernels(int fp64, int n);
+
+}  // namespace swf
