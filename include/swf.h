@@ -132,6 +132,10 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms,
  * SWF_E_ORDER if n_steps exceeds the steps left; SWF_E_ARG if n_steps < 0. */
 swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left);
 
+/* Return every solve to psi_s(t_out) = 0 at step 0 and clear the BW integrals,
+ * keeping the plan, tables and captured graph (to run the same job again). */
+swf_status swf_reset(swf_ctx* ctx);
+
 /* Wait for the context's queued work.  SWF_E_HIP on a device error. */
 swf_status swf_sync(swf_ctx* ctx);
 
@@ -197,6 +201,9 @@ int swf_supported_n(int n);
 
 /* Total steps of the context's window; current step index. */
 swf_status swf_steps(swf_ctx* ctx, int* total, int* done);
+
+/* Text report of the autotuner run at init (variant timings per group), or "". */
+const char* swf_tune_report(const swf_ctx* ctx);
 
 const char* swf_last_error(const swf_ctx* ctx);
 void swf_free(swf_ctx* ctx);

@@ -35,10 +35,14 @@ def _jobs():
 
 
 def _compile(unit):
+    import time
     src, defs, obj = unit
     cmd = [HIPCC] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", os.path.join(OUT, obj)]
+    t0 = time.time()
     p = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (p.stderr or "").splitlines() if "packed-fp32-ops" not in l)
+    if os.environ.get("SWF_BUILD_TIMES"):
+        print(f"{obj}: {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     return obj, p.returncode, err
 
 

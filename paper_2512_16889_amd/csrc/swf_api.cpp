@@ -9,7 +9,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <sstream>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -131,8 +136,10 @@ struct Group {
     int grid;
     std::vector<int> solves;
     const swf::SizeKernels* k[3] = {nullptr, nullptr, nullptr};
-    size_t it_row = 0, it_coly = 0, it_colz = 0;  // offsets (int2) into the item array
-    int n_row = 0, n_coly = 0, n_colz = 0;
+    // offsets (int2) into the item array and counts, per tile variant
+    size_t it_row[swf::NVAR] = {}, it_coly[swf::NVAR] = {}, it_colz[swf::NVAR] = {};
+    int n_row[swf::NVAR] = {}, n_coly[swf::NVAR] = {}, n_colz[swf::NVAR] = {};
+    int vr = 0, vy = 0, vz = 0;   // tile variants in use
 };
 
 struct Plan {
@@ -174,24 +181,26 @@ static void add_items(Plan& P, Group& g, int fp64) {
     g.k[0] = swf::size_kernels(fp64, n0);
     if (G.dim >= 2) g.k[1] = swf::size_kernels(fp64, n1);
     if (G.dim >= 3) g.k[2] = swf::size_kernels(fp64, n2);
-    g.it_row = P.items.size();
-    const int rows = g.k[0]->row_rows;
-    for (int s : g.solves)
-        for (int tile = 0; tile < (n1 * n2 + rows - 1) / rows; ++tile) P.items.push_back(make_int2(s, tile));
-    g.n_row = (int)(P.items.size() - g.it_row);
-    if (G.dim >= 2) {
-        g.it_coly = P.items.size();
-        const int ntx = (n0 + g.k[1]->col_w - 1) / g.k[1]->col_w;
+    for (int v = 0; v < swf::NVAR; ++v) {
+        g.it_row[v] = P.items.size();
+        const int rows = g.k[0]->row[v].rows;
         for (int s : g.solves)
-            for (int tile = 0; tile < ntx * n2; ++tile) P.items.push_back(make_int2(s, tile));
-        g.n_coly = (int)(P.items.size() - g.it_coly);
-    }
-    if (G.dim >= 3) {
-        g.it_colz = P.items.size();
-        const int ntx = (n0 + g.k[2]->col_w - 1) / g.k[2]->col_w;
-        for (int s : g.solves)
-            for (int tile = 0; tile < ntx * n1; ++tile) P.items.push_back(make_int2(s, tile));
-        g.n_colz = (int)(P.items.size() - g.it_colz);
+            for (int tile = 0; tile < (n1 * n2 + rows - 1) / rows; ++tile) P.items.push_back(make_int2(s, tile));
+        g.n_row[v] = (int)(P.items.size() - g.it_row[v]);
+        if (G.dim >= 2) {
+            g.it_coly[v] = P.items.size();
+            const int ntx = (n0 + g.k[1]->col[v].w - 1) / g.k[1]->col[v].w;
+            for (int s : g.solves)
+                for (int tile = 0; tile < ntx * n2; ++tile) P.items.push_back(make_int2(s, tile));
+            g.n_coly[v] = (int)(P.items.size() - g.it_coly[v]);
+        }
+        if (G.dim >= 3) {
+            g.it_colz[v] = P.items.size();
+            const int ntx = (n0 + g.k[2]->col[v].w - 1) / g.k[2]->col[v].w;
+            for (int s : g.solves)
+                for (int tile = 0; tile < ntx * n1; ++tile) P.items.push_back(make_int2(s, tile));
+            g.n_colz[v] = (int)(P.items.size() - g.it_colz[v]);
+        }
     }
 }
 
@@ -466,6 +475,8 @@ struct swf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::string err;
+    std::string tune_path;
+    std::string tune_report;
     // profiling
     std::vector<hipEvent_t> ev_free;
     std::vector<PendingEv> pending;
@@ -583,7 +594,8 @@ static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threa
 }
 
 // x-axis pass of a group in the given mode.
-static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, int dst, double tex, long long ph2) {
+static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, int dst, double tex, long long ph2,
+                    int kind = 4) {
     const auto* k = g.k[0];
     swf::PassArgs a = pass_args(ctx);
     a.stage = stage;
@@ -595,30 +607,36 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     double trav = 2;
     if (mode == swf::ROW_STAGE) trav = (stage == 0 || stage == 3) ? 5 : 7;
     else if (mode == swf::ROW_RHS) trav = 3;
-    return launch(ctx, k->row[mode], g.n_row, g.it_row, k->row_threads, k->row_lds, a, 0,
-                  trav * 4.0 * ctx->P.csize * group_sites(ctx, g));
+    const double bytes = trav * 4.0 * ctx->P.csize * group_sites(ctx, g);
+    if (mode == swf::ROW_STAGE) {
+        const auto& v = k->row[g.vr];
+        return launch(ctx, v.stage, g.n_row[g.vr], g.it_row[g.vr], v.threads, v.lds, a, kind, bytes);
+    }
+    return launch(ctx, k->row_other[mode], g.n_row[0], g.it_row[0], k->row0_threads, k->row0_lds, a, kind, bytes);
 }
 
-static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role) {
-    const auto* k = g.k[axis];
+static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, int kind = 4) {
+    const int v = axis == 1 ? g.vy : g.vz;
+    const auto& cv = g.k[axis]->col[v];
     swf::PassArgs a = pass_args(ctx);
     a.dst = role;
     a.src = role;
-    const int n = axis == 1 ? g.n_coly : g.n_colz;
-    const size_t it = axis == 1 ? g.it_coly : g.it_colz;
-    return launch(ctx, k->col[axis - 1][mode], n, it, k->col_threads, k->col_lds, a, axis,
+    const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
+    const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
+    return launch(ctx, cv.fn[axis - 1][mode], n, it, cv.threads, cv.lds, a, kind,
                   2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g));
 }
 
 // k-space kinetic pass of a group (between the forward x pass and the row epilogue).
-static int kinetic_cols(swf_ctx* ctx, const Group& g, int role) {
+static int kinetic_cols(swf_ctx* ctx, const Group& g, int role, bool stepping) {
     const int dim = ctx->P.grids[g.grid].dim;
+    const int ky = stepping ? 1 : 4, kz = stepping ? 2 : 4;
     int r = SWF_OK;
-    if (dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, role);
+    if (dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, role, ky);
     if (dim == 3) {
-        r = col_pass(ctx, g, 1, swf::COL_FWD, role);
-        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, role);
-        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, role);
+        r = col_pass(ctx, g, 1, swf::COL_FWD, role, ky);
+        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, role, kz);
+        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, role, ky);
     }
     return r;
 }
@@ -688,8 +706,8 @@ static int enqueue_step(swf_ctx* ctx) {
         int r = bw_stage(ctx, s);
         if (r) return r;
         for (const auto& g : groups(ctx)) {
-            r = kinetic_cols(ctx, g, swf::BUF_T);
-            if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0);
+            r = kinetic_cols(ctx, g, swf::BUF_T, true);
+            if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0, 0);
             if (r) return r;
         }
     }
@@ -711,6 +729,105 @@ static int build_graph(swf_ctx* ctx) {
     }
     ctx->graph = g;
     HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    return SWF_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// Times every tile variant of the three stepping passes of each group on the
+// problem itself (zero state, stage 1), keeps the fastest, and caches the
+// choice by (precision, grid, batch size) in a text file.
+static std::string tune_key(swf_ctx* ctx, const Group& g) {
+    const swf_grid& G = ctx->P.grids[g.grid];
+    char b[160];
+    snprintf(b, sizeof(b), "%s d%d n%dx%dx%d b%zu", ctx->P.fp64 ? "f64" : "f32", G.dim, G.n[0], G.n[1], G.n[2],
+             g.solves.size());
+    return b;
+}
+
+static int time_it(swf_ctx* ctx, const std::function<int()>& f, int reps, float* ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    int r = f();
+    if (!r) {
+        HIPCHK(hipEventRecord(a, ctx->st));
+        for (int i = 0; i < reps && !r; ++i) r = f();
+        HIPCHK(hipEventRecord(b, ctx->st));
+        HIPCHK(hipEventSynchronize(b));
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, a, b));
+        *ms = t / reps;
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return r;
+}
+
+static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
+    std::map<std::string, std::array<int, 3>> cache;
+    if (!ctx->tune_path.empty()) {
+        std::ifstream in(ctx->tune_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find('|');
+            if (bar == std::string::npos) continue;
+            std::istringstream vs(line.substr(bar + 1));
+            std::array<int, 3> v{0, 0, 0};
+            vs >> v[0] >> v[1] >> v[2];
+            if (vs) cache[line.substr(0, bar)] = v;
+        }
+    }
+    const int prof = ctx->opt.profile;
+    ctx->opt.profile = 0;
+    std::ostringstream rep;
+    for (auto& g : gl) {
+        const std::string key = tune_key(ctx, g);
+        auto it = cache.find(key);
+        const int dim = ctx->P.grids[g.grid].dim;
+        if (it != cache.end()) {
+            g.vr = std::min(it->second[0], swf::NVAR - 1);
+            g.vy = std::min(it->second[1], swf::NVAR - 1);
+            g.vz = std::min(it->second[2], swf::NVAR - 1);
+            rep << key << ": cached " << g.vr << " " << g.vy << " " << g.vz << "\n";
+            continue;
+        }
+        const int reps = 4;
+        float best = 1e30f;
+        int bv = 0;
+        for (int v = 0; v < g.k[0]->nvar; ++v) {
+            g.vr = v;
+            float ms = 0;
+            int r = time_it(ctx, [&] { return row_pass(ctx, g, swf::ROW_STAGE, 1, 0, 0, 0, 0, 4); }, reps, &ms);
+            if (r) { ctx->opt.profile = prof; return r; }
+            rep << key << ": row v" << v << " " << ms << " ms\n";
+            if (ms < best) { best = ms; bv = v; }
+        }
+        g.vr = bv;
+        for (int axis = 1; axis < dim; ++axis) {
+            const int mode = (axis == dim - 1) ? swf::COL_H0 : swf::COL_FWD;
+            best = 1e30f;
+            bv = 0;
+            for (int v = 0; v < g.k[axis]->nvar; ++v) {
+                (axis == 1 ? g.vy : g.vz) = v;
+                float ms = 0;
+                int r = time_it(ctx, [&] { return col_pass(ctx, g, axis, mode, swf::BUF_T, 4); }, reps, &ms);
+                if (r) { ctx->opt.profile = prof; return r; }
+                rep << key << ": col" << axis << " v" << v << " " << ms << " ms\n";
+                if (ms < best) { best = ms; bv = v; }
+            }
+            (axis == 1 ? g.vy : g.vz) = bv;
+        }
+        cache[key] = {g.vr, g.vy, g.vz};
+        if (!ctx->tune_path.empty()) {
+            std::ofstream out(ctx->tune_path, std::ios::app);
+            out << key << "|" << g.vr << " " << g.vy << " " << g.vz << "\n";
+        }
+    }
+    ctx->opt.profile = prof;
+    ctx->tune_report = rep.str();
+    // the tuning launches stepped the state: start from psi_s(t_out) = 0 again
+    HIPCHK(hipMemsetAsync(ctx->arena + ctx->P.off_state, 0, ctx->P.state_bytes, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
     return SWF_OK;
 }
 
@@ -962,6 +1079,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         return (swf_status)r;
     }
     ctx->opt = *opt;
+    if (opt->tune_cache) ctx->tune_path = opt->tune_cache;
     ctx->opt.tune_cache = nullptr;
     ctx->user = (hipStream_t)opt->stream;
     auto fail = [&](int code) {
@@ -1038,14 +1156,21 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 const auto* k = g.k[ax];
                 if (!k) continue;
                 for (int m = 0; m < 5; ++m)
-                    INITCHK(hipFuncSetAttribute(k->row[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row_lds));
-                for (int a = 0; a < 2; ++a)
-                    for (int m = 0; m < 3; ++m)
-                        INITCHK(hipFuncSetAttribute(k->col[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col_lds));
+                    INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
+                for (int v = 0; v < swf::NVAR; ++v) {
+                    INITCHK(hipFuncSetAttribute(k->row[v].stage, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
+                    for (int a = 0; a < 2; ++a)
+                        for (int m = 0; m < 3; ++m)
+                            INITCHK(hipFuncSetAttribute(k->col[v].fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col[v].lds));
+                }
             }
     ctx->kvalid.assign(P.solves.size(), 0);
     ctx->bw_done.assign(P.hv.size(), 0);
     ctx->bw_cache.assign(6 * P.hv.size(), cd(0));
+    if (opt->tune) {
+        int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
+        if (rr) return fail(rr);
+    }
     if (opt->use_graph && !opt->profile) {
         int rr = build_graph(ctx);
         if (rr) return fail(rr);
@@ -1086,6 +1211,21 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
     if (r) return (swf_status)r;
     if (steps_left) *steps_left = ctx->P.steps - ctx->step;
     return SWF_OK;
+}
+
+swf_status swf_reset(swf_ctx* ctx) {
+    if (!ctx) return SWF_E_ARG;
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    HIPCHK(hipMemsetAsync(ctx->arena + ctx->P.off_state, 0, ctx->P.state_bytes, ctx->st));
+    HIPCHK(hipMemsetAsync(ctx->d_step(), 0, 256, ctx->st));
+    HIPCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, ctx->P.hv.size()), ctx->st));
+    ctx->step = 0;
+    ctx->t_valid = true;
+    std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
+    std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
+    r = leave(ctx);
+    return (swf_status)r;
 }
 
 swf_status swf_sync(swf_ctx* ctx) {
@@ -1299,7 +1439,7 @@ swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in,
         if (dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_T);
         if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_T);
     } else {
-        r = kinetic_cols(ctx, g, swf::BUF_T);
+        r = kinetic_cols(ctx, g, swf::BUF_T, false);
         if (!r) r = row_pass(ctx, g, op == 1 ? swf::ROW_INV : swf::ROW_RHS, 0, swf::BUF_YS, swf::BUF_ACC, t, 0);
         role_out = swf::BUF_ACC;
     }
@@ -1338,6 +1478,8 @@ swf_status swf_steps(swf_ctx* ctx, int* total, int* done) {
     if (done) *done = ctx->step;
     return SWF_OK;
 }
+
+const char* swf_tune_report(const swf_ctx* ctx) { return ctx ? ctx->tune_report.c_str() : ""; }
 
 const char* swf_last_error(const swf_ctx* ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
 

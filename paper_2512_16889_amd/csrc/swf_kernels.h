@@ -36,35 +36,59 @@ struct PassArgs {
     long long ph2;         // ROW_FWDPH: complex offset of exp(i k_j x_j) tables
 };
 
-template <int N> struct RowCfg {
-    static constexpr int T = FftPlan<N>::T;
-    static constexpr int ROWS = (256 / T) > 0 ? (256 / T) : 1;
+// ------------------------------------------------------------------ tile variants
+// A pass kernel is instantiated for several tile shapes; the host times them on
+// the actual problem (autotuner) and keeps the fastest.
+//   row pass: T threads per x-line, ROWS lines per block, CG components per
+//             LDS exchange round;
+//   column pass: T threads per line, W adjacent x-columns per block, CG.
+template <int N, int T> constexpr bool plan_ok() {
+    if (T < 1 || N % T) return false;
+    for (int j = 0; j < FftPlan<N>::NR; ++j)
+        if ((N / FftPlan<N>::R[j]) % T || (N / T) % FftPlan<N>::R[j]) return false;
+    return true;
+}
+template <int N> constexpr int half_t() {
+    constexpr int T = FftPlan<N>::T;
+    return (T % 2 == 0 && 2 * N / T <= 16 && plan_ok<N, T / 2>()) ? T / 2 : T;
+}
+constexpr int NVAR = 4;
+template <int N> constexpr int nvar() { return N >= 256 ? NVAR : 1; }
+constexpr size_t LDS_CAP = 72 * 1024;
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int cg_fit(size_t per_comp) { return 4 * per_comp <= LDS_CAP ? 4 : (2 * per_comp <= LDS_CAP ? 2 : 1); }
+
+template <class R, int N, int V> struct RowVar {
+    static constexpr int T = (V == 3) ? half_t<N>() : FftPlan<N>::T;
+    static constexpr int ROWS = imax(1, (V == 2 ? 128 : 256) / T);
     static constexpr int THREADS = T * ROWS;
+    using Lay = RowLay<N, ROWS>;
+    static constexpr size_t PER_COMP = (size_t)ROWS * Lay::STRIDE * sizeof(cpx<R>);
+    static constexpr int CG = V == 0 ? 1 : cg_fit(PER_COMP);
+    static constexpr size_t BYTES = CG * PER_COMP;
 };
 
-template <class R, int N> struct RowLds {
-    using Lay = RowLay<N, RowCfg<N>::ROWS>;
-    static constexpr int CG = 1;
-    static constexpr size_t BYTES = (size_t)CG * RowCfg<N>::ROWS * Lay::STRIDE * sizeof(cpx<R>);
-};
-
-template <class R, int N> struct ColCfg {
-    static constexpr int T = FftPlan<N>::T;
+template <class R, int N, int V> struct ColVar {
     static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;
-    static constexpr int W = (T * WANT <= 512) ? WANT : (512 / T);
+    static constexpr int T = (V >= 2) ? half_t<N>() : FftPlan<N>::T;
+    static constexpr int W = imax(1, imin(V == 2 ? 2 * WANT : WANT, 512 / T));
     static constexpr int THREADS = T * W;
-    static constexpr size_t BYTES = (size_t)N * W * sizeof(cpx<R>);
+    static constexpr size_t PER_COMP = (size_t)N * W * sizeof(cpx<R>);
+    static constexpr int CG = (V == 1 || V == 3) ? imin(2, cg_fit(PER_COMP)) : 1;
+    static constexpr size_t BYTES = CG * PER_COMP;
 };
 
 // ------------------------------------------------------------------ row pass
-template <class R, int N, int MODE>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS) row_kernel(PassArgs a) {
+template <class R, int N, int V, int MODE>
+__global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArgs a) {
     using C = cpx<R>;
-    constexpr int T = RowCfg<N>::T;
-    constexpr int ROWS = RowCfg<N>::ROWS;
+    using VC = RowVar<R, N, V>;
+    constexpr int T = VC::T;
+    constexpr int ROWS = VC::ROWS;
     constexpr int E = N / T;
-    using Lay = typename RowLds<R, N>::Lay;
-    constexpr int CG = RowLds<R, N>::CG;
+    using Lay = typename VC::Lay;
+    constexpr int CG = VC::CG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
     __shared__ R sh_fyz[ROWS][MAX_TERMS];
@@ -162,7 +186,7 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_kernel(PassArgs a) {
                     sh_tab[j] = tm.tab;
                 }
             }
-            for (int q = tid; q < 4; q += RowCfg<N>::THREADS) {
+            for (int q = tid; q < 4; q += VC::THREADS) {
                 double sn, cs;
                 sincos(-S->E * ts, &sn, &cs);
                 const double wr = S->w[2 * q], wi = S->w[2 * q + 1];
@@ -270,11 +294,13 @@ __global__ void __launch_bounds__(RowCfg<N>::THREADS) row_kernel(PassArgs a) {
 }
 
 // ------------------------------------------------------------------ column pass
-template <class R, int N, int MODE, int AXIS>
-__global__ void __launch_bounds__((ColCfg<R, N>::THREADS)) col_kernel(PassArgs a) {
+template <class R, int N, int V, int MODE, int AXIS>
+__global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArgs a) {
     using C = cpx<R>;
-    constexpr int T = ColCfg<R, N>::T;
-    constexpr int W = ColCfg<R, N>::W;
+    using VC = ColVar<R, N, V>;
+    constexpr int T = VC::T;
+    constexpr int W = VC::W;
+    constexpr int CG = VC::CG;
     constexpr int E = N / T;
     using Lay = ColLay<N, W>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -302,7 +328,7 @@ __global__ void __launch_bounds__((ColCfg<R, N>::THREADS)) col_kernel(PassArgs a
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int m = 0; m < E; ++m) v[q][m] = buf[q * ns + base + (long long)(t + T * m) * stride];
-    if constexpr (MODE == COL_FWD || MODE == COL_H0) fft_line<C, N, T, -1, 4, 1, Lay>(v, lds, t, xl, tw);
+    if constexpr (MODE == COL_FWD || MODE == COL_H0) fft_line<C, N, T, -1, 4, CG, Lay>(v, lds, t, xl, tw);
     if constexpr (MODE == COL_H0) {
         const R s = (R)S->inv_n;
         const R Kx = (R)(S->dk[0] * kindex(act ? x : 0, n0));
@@ -320,7 +346,7 @@ __global__ void __launch_bounds__((ColCfg<R, N>::THREADS)) col_kernel(PassArgs a
             apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
         }
     }
-    if constexpr (MODE == COL_INV || MODE == COL_H0) fft_line<C, N, T, +1, 4, 1, Lay>(v, lds, t, xl, tw);
+    if constexpr (MODE == COL_INV || MODE == COL_H0) fft_line<C, N, T, +1, 4, CG, Lay>(v, lds, t, xl, tw);
     if (act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -330,35 +356,65 @@ __global__ void __launch_bounds__((ColCfg<R, N>::THREADS)) col_kernel(PassArgs a
 }
 
 // Kernel table of one (precision, N) instantiation.
+struct RowVariant { const void* stage; int threads, rows; size_t lds; };
+struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
-    const void* row[5];       // by row mode
-    const void* col[2][3];    // [axis-1][col mode]
-    int row_threads, row_rows;
-    size_t row_lds;
-    int col_threads, col_w;
-    size_t col_lds;
+    int nvar;
+    RowVariant row[NVAR];          // the RK4 stage pass, by variant
+    const void* row_other[5];      // other row modes (variant 0)
+    int row0_threads, row0_rows;
+    size_t row0_lds;
+    ColVariant col[NVAR];
 };
+
+template <class R, int N, int V>
+RowVariant make_row_variant() {
+    using VC = RowVar<R, N, V>;
+    return RowVariant{(const void*)row_kernel<R, N, V, ROW_STAGE>, VC::THREADS, VC::ROWS, VC::BYTES};
+}
+template <class R, int N, int V>
+ColVariant make_col_variant() {
+    using VC = ColVar<R, N, V>;
+    ColVariant c;
+    c.fn[0][COL_FWD] = (const void*)col_kernel<R, N, V, COL_FWD, 1>;
+    c.fn[0][COL_INV] = (const void*)col_kernel<R, N, V, COL_INV, 1>;
+    c.fn[0][COL_H0] = (const void*)col_kernel<R, N, V, COL_H0, 1>;
+    c.fn[1][COL_FWD] = (const void*)col_kernel<R, N, V, COL_FWD, 2>;
+    c.fn[1][COL_INV] = (const void*)col_kernel<R, N, V, COL_INV, 2>;
+    c.fn[1][COL_H0] = (const void*)col_kernel<R, N, V, COL_H0, 2>;
+    c.threads = VC::THREADS;
+    c.w = VC::W;
+    c.lds = VC::BYTES;
+    return c;
+}
 
 template <class R, int N>
 SizeKernels make_size_kernels() {
     SizeKernels k;
-    k.row[ROW_FWD] = (const void*)row_kernel<R, N, ROW_FWD>;
-    k.row[ROW_STAGE] = (const void*)row_kernel<R, N, ROW_STAGE>;
-    k.row[ROW_INV] = (const void*)row_kernel<R, N, ROW_INV>;
-    k.row[ROW_RHS] = (const void*)row_kernel<R, N, ROW_RHS>;
-    k.row[ROW_FWDPH] = (const void*)row_kernel<R, N, ROW_FWDPH>;
-    k.col[0][COL_FWD] = (const void*)col_kernel<R, N, COL_FWD, 1>;
-    k.col[0][COL_INV] = (const void*)col_kernel<R, N, COL_INV, 1>;
-    k.col[0][COL_H0] = (const void*)col_kernel<R, N, COL_H0, 1>;
-    k.col[1][COL_FWD] = (const void*)col_kernel<R, N, COL_FWD, 2>;
-    k.col[1][COL_INV] = (const void*)col_kernel<R, N, COL_INV, 2>;
-    k.col[1][COL_H0] = (const void*)col_kernel<R, N, COL_H0, 2>;
-    k.row_threads = RowCfg<N>::THREADS;
-    k.row_rows = RowCfg<N>::ROWS;
-    k.row_lds = RowLds<R, N>::BYTES;
-    k.col_threads = ColCfg<R, N>::THREADS;
-    k.col_w = ColCfg<R, N>::W;
-    k.col_lds = ColCfg<R, N>::BYTES;
+    k.nvar = nvar<N>();
+    k.row[0] = make_row_variant<R, N, 0>();
+    k.col[0] = make_col_variant<R, N, 0>();
+    if constexpr (nvar<N>() > 1) {
+        k.row[1] = make_row_variant<R, N, 1>();
+        k.row[2] = make_row_variant<R, N, 2>();
+        k.row[3] = make_row_variant<R, N, 3>();
+        k.col[1] = make_col_variant<R, N, 1>();
+        k.col[2] = make_col_variant<R, N, 2>();
+        k.col[3] = make_col_variant<R, N, 3>();
+    } else {
+        for (int v = 1; v < NVAR; ++v) {
+            k.row[v] = k.row[0];
+            k.col[v] = k.col[0];
+        }
+    }
+    k.row_other[ROW_FWD] = (const void*)row_kernel<R, N, 0, ROW_FWD>;
+    k.row_other[ROW_STAGE] = (const void*)row_kernel<R, N, 0, ROW_STAGE>;
+    k.row_other[ROW_INV] = (const void*)row_kernel<R, N, 0, ROW_INV>;
+    k.row_other[ROW_RHS] = (const void*)row_kernel<R, N, 0, ROW_RHS>;
+    k.row_other[ROW_FWDPH] = (const void*)row_kernel<R, N, 0, ROW_FWDPH>;
+    k.row0_threads = RowVar<R, N, 0>::THREADS;
+    k.row0_rows = RowVar<R, N, 0>::ROWS;
+    k.row0_lds = RowVar<R, N, 0>::BYTES;
     return k;
 }
 

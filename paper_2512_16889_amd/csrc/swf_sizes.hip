@@ -27,23 +27,23 @@ SWF_DEFINE(16)
 SWF_DEFINE(32)
 SWF_DEFINE(64)
 SWF_DEFINE(128)
-#elif SWF_GROUP == 1
 SWF_DEFINE(48)
 SWF_DEFINE(96)
 SWF_DEFINE(40)
 SWF_DEFINE(80)
-#elif SWF_GROUP == 2
+SWF_DEFINE(160)
+SWF_DEFINE(192)
+#elif SWF_GROUP == 1
 SWF_DEFINE(256)
+#elif SWF_GROUP == 2
 SWF_DEFINE(512)
 #elif SWF_GROUP == 3
 SWF_DEFINE(1024)
 #elif SWF_GROUP == 4
-SWF_DEFINE(192)
 SWF_DEFINE(384)
 #elif SWF_GROUP == 5
 SWF_DEFINE(768)
 #elif SWF_GROUP == 6
-SWF_DEFINE(160)
 SWF_DEFINE(320)
 #endif
 

@@ -73,6 +73,7 @@ _lib.swf_init.argtypes = [_P(Grid), C.c_int, _P(Term), _P(C.c_int), C.c_int, _P(
                           _P(Vertex), C.c_int, _P(Window), _P(Options), _P(C.c_void_p)]
 _lib.swf_step.argtypes = [C.c_void_p, C.c_int, _P(C.c_int)]
 _lib.swf_sync.argtypes = [C.c_void_p]
+_lib.swf_reset.argtypes = [C.c_void_p]
 _lib.swf_amplitude.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _P(C.c_double)]
 _lib.swf_probability.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _P(C.c_double)]
 _lib.swf_diagnostics.argtypes = [C.c_void_p, C.c_int, _P(C.c_double)]
@@ -85,15 +86,17 @@ _lib.swf_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_longlong), _P(C.c_
 _lib.swf_reset_stats.argtypes = [C.c_void_p]
 _lib.swf_steps.argtypes = [C.c_void_p, _P(C.c_int), _P(C.c_int)]
 _lib.swf_supported_n.argtypes = [C.c_int]
+_lib.swf_tune_report.argtypes = [C.c_void_p]
+_lib.swf_tune_report.restype = C.c_char_p
 _lib.swf_last_error.argtypes = [C.c_void_p]
 _lib.swf_last_error.restype = C.c_char_p
 _lib.swf_free.argtypes = [C.c_void_p]
 _lib.swf_free.restype = None
 
-EXPORTED = ["swf_workspace_size", "swf_init", "swf_step", "swf_sync", "swf_amplitude", "swf_probability",
+EXPORTED = ["swf_workspace_size", "swf_init", "swf_step", "swf_reset", "swf_sync", "swf_amplitude", "swf_probability",
             "swf_diagnostics", "swf_get_psi", "swf_set_psi", "swf_get_bw_state", "swf_set_bw_state",
             "swf_apply_op", "swf_kernel_stats", "swf_reset_stats", "swf_supported_n", "swf_steps",
-            "swf_last_error", "swf_free"]
+            "swf_tune_report", "swf_last_error", "swf_free"]
 
 
 class SwfError(RuntimeError):
@@ -155,7 +158,8 @@ class Context:
     """One swf_ctx: all solves of a problem, stepped together."""
 
     def __init__(self, problem, precision: str = "fp64", use_graph: bool = False, batched: bool = True,
-                 profile: bool = False, device_workspace: bool = True):
+                 profile: bool = False, device_workspace: bool = True, tune: bool = False,
+                 tune_cache: str | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("the SWF solver runs on the GPU only; no device is visible")
         self.problem = problem
@@ -166,6 +170,9 @@ class Context:
         self.opt.use_graph = int(use_graph)
         self.opt.batched = int(batched)
         self.opt.profile = int(profile)
+        self.opt.tune = int(tune)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        self.opt.tune_cache = self._tune_cache
         self.opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
         nbytes = C.c_size_t(0)
         args = (grids, len(problem.grids), terms, ffirst, len(problem.fields), solves, len(problem.solves),
@@ -217,6 +224,9 @@ class Context:
 
     def sync(self):
         self._check(_lib.swf_sync(self._ctx))
+
+    def reset(self):
+        self._check(_lib.swf_reset(self._ctx))
 
     def steps(self):
         t, d = C.c_int(0), C.c_int(0)
@@ -296,6 +306,9 @@ class Context:
         n, ms, by = C.c_longlong(0), C.c_double(0), C.c_double(0)
         self._check(_lib.swf_kernel_stats(self._ctx, kind, C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
+
+    def tune_report(self) -> str:
+        return _lib.swf_tune_report(self._ctx).decode()
 
     def reset_stats(self):
         self._check(_lib.swf_reset_stats(self._ctx))
