@@ -61,8 +61,9 @@ def run_job(ctx, prob):
     return out
 
 
-def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True):
-    ctx = S.Context(prob, precision=precision, batched=batched, use_graph=graph, profile=profile, tune=tune)
+def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True, chunk=0):
+    ctx = S.Context(prob, precision=precision, batched=batched, use_graph=graph, profile=profile, tune=tune,
+                    chunk=chunk)
     report = ctx.tune_report()
     results = None
     for _ in range(W):
@@ -131,7 +132,21 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=300)
+    ap.add_argument("--chunk", type=int, default=0, help="solves per launch group (0 = all)")
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile variants")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: every solve of a job is independent and "
                           "the multi-GPU sharding is described, not built; run with --gpus 1"}))
@@ -147,7 +162,8 @@ def main():
     print(f"[bench] workload {desc}; {len(prob.solves)} solves, {steps} RK4 steps, {su:.3e} site-updates per job",
           file=sys.stderr, flush=True)
 
-    wall, P_mixed, stats, tune_rep = timed_jobs(S, torch, prob, "mixed", args.steps, args.warmup)
+    wall, P_mixed, stats, tune_rep = timed_jobs(S, torch, prob, "mixed", args.steps, args.warmup, chunk=args.chunk,
+                                                tune=not args.no_tune)
     print("[bench] autotune:\n" + tune_rep, file=sys.stderr, flush=True)
     value = su * args.steps / wall
     print(f"[bench] mixed batched: {wall:.2f} s for {args.steps} job(s) -> {value:.4e} site-updates/s",
@@ -166,7 +182,7 @@ def main():
 
     extra = {}
     if not args.no_fp64:
-        wall64, P64, _, _ = timed_jobs(S, torch, prob, "fp64", 1, 0, profile=False)
+        wall64, P64, _, _ = timed_jobs(S, torch, prob, "fp64", 1, 0, profile=False, chunk=args.chunk)
         extra["fp64_batched"] = {"value": su / wall64, "ms_per_step": wall64 * 1e3}
         rel = [abs(a - b) / abs(b) for a, b in zip(P_mixed, P64) if b != 0]
         extra["p_rel_err_mixed_vs_fp64"] = {"max": max(rel), "median": float(np.median(rel)),
@@ -192,7 +208,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "solves": len(prob.solves), "grid": prob.grids[0].n[:prob.grids[0].dim],
                    "rk4_steps": steps, "precision": "mixed: complex64 state/FFT, FP64 phases, times, reductions",
-                   "parallelism": "single GPU, batched solves"},
+                   "parallelism": "single GPU, batched solves", "chunk": args.chunk},
         "roofline": {"bound": "hbm", "kernel": names.get(dom, str(dom)), "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": by / max(n_l, 1)},

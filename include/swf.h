@@ -106,6 +106,10 @@ typedef struct {
     int profile;            /* 1: time every pass with HIP events (see swf_kernel_stats) */
     int tune;               /* 1: autotune tile shapes at init (results cached)         */
     const char* tune_cache; /* path of the tune cache file, or NULL                     */
+    int chunk;              /* batched mode: at most this many solves per launch group
+                               (0 = all solves of a grid size).  Without BW vertices a
+                               time step then runs all passes of one chunk before the
+                               next, so a chunk's arrays can stay in the on-die cache  */
 } swf_options;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */

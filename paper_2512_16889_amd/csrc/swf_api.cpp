@@ -175,6 +175,18 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
         return code;                                                 \
     } while (0)
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// The G column tiles that share 128-byte lines (x-adjacent tiles) are placed 8
+// blocks apart so they all land on the same XCD and its L2 serves all but the
+// first of them.
+static void xcd_group_order(std::vector<int2>& items, size_t first, int G) {
+    if (G <= 1) return;
+    const size_t n = items.size() - first, span = 8 * (size_t)G;
+    std::vector<int2> tmp(items.begin() + first, items.end());
+    for (size_t i = 0; i + span <= n; i += span)
+        for (size_t j = 0; j < span; ++j) items[first + i + (j % G) * 8 + j / G] = tmp[i + j];
+}
+
 static void add_items(Plan& P, Group& g, int fp64) {
     const swf_grid& G = P.grids[g.grid];
     const int n0 = G.n[0], n1 = G.dim >= 2 ? G.n[1] : 1, n2 = G.dim >= 3 ? G.n[2] : 1;
@@ -193,6 +205,7 @@ static void add_items(Plan& P, Group& g, int fp64) {
             for (int s : g.solves)
                 for (int tile = 0; tile < ntx * n2; ++tile) P.items.push_back(make_int2(s, tile));
             g.n_coly[v] = (int)(P.items.size() - g.it_coly[v]);
+            xcd_group_order(P.items, g.it_coly[v], std::max(1, 128 / (g.k[1]->col[v].w * (int)P.csize)));
         }
         if (G.dim >= 3) {
             g.it_colz[v] = P.items.size();
@@ -200,6 +213,7 @@ static void add_items(Plan& P, Group& g, int fp64) {
             for (int s : g.solves)
                 for (int tile = 0; tile < ntx * n1; ++tile) P.items.push_back(make_int2(s, tile));
             g.n_colz[v] = (int)(P.items.size() - g.it_colz[v]);
+            xcd_group_order(P.items, g.it_colz[v], std::max(1, 128 / (g.k[2]->col[v].w * (int)P.csize)));
         }
     }
 }
@@ -408,13 +422,18 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         P.hv.push_back(d);
     }
     // ---- groups and work items
+    if (opt->chunk < 0) FAIL(SWF_E_ARG, "chunk must be >= 0");
     for (int g = 0; g < n_grids; ++g) {
-        Group gr;
-        gr.grid = g;
-        for (int i = 0; i < n_solves; ++i) if (P.solves[i].grid == g) gr.solves.push_back(i);
-        if (gr.solves.empty()) continue;
-        add_items(P, gr, P.fp64);
-        P.batched.push_back(gr);
+        std::vector<int> all;
+        for (int i = 0; i < n_solves; ++i) if (P.solves[i].grid == g) all.push_back(i);
+        const size_t cs = opt->chunk > 0 ? (size_t)opt->chunk : std::max<size_t>(1, all.size());
+        for (size_t a = 0; a < all.size(); a += cs) {
+            Group gr;
+            gr.grid = g;
+            gr.solves.assign(all.begin() + a, all.begin() + std::min(all.size(), a + cs));
+            add_items(P, gr, P.fp64);
+            P.batched.push_back(gr);
+        }
     }
     for (int i = 0; i < n_solves; ++i) {
         Group gr;
@@ -573,9 +592,11 @@ static double group_sites(swf_ctx* ctx, const Group& g) {
 
 // Launch one pass kernel over n items starting at item offset `it`.
 static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threads, size_t lds, swf::PassArgs a,
-                  int kind, double bytes) {
+                  int kind, double bytes, int tiles = 1) {
     if (nitems <= 0) return SWF_OK;
     a.items = ctx->d_items() + it;
+    a.nitems = nitems;
+    const int blocks = (nitems + tiles - 1) / tiles;
     void* args[] = {&a};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = ctx->opt.profile && !ctx->gexec;
@@ -585,7 +606,7 @@ static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threa
         if (r) return r;
         HIPCHK(hipEventRecord(e0, ctx->st));
     }
-    HIPCHK(hipLaunchKernel(fn, dim3(nitems), dim3(threads), args, lds, ctx->st));
+    HIPCHK(hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, ctx->st));
     if (prof) {
         HIPCHK(hipEventRecord(e1, ctx->st));
         ctx->pending.push_back({e0, e1, kind, bytes});
@@ -610,7 +631,7 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     const double bytes = trav * 4.0 * ctx->P.csize * group_sites(ctx, g);
     if (mode == swf::ROW_STAGE) {
         const auto& v = k->row[g.vr];
-        return launch(ctx, v.stage, g.n_row[g.vr], g.it_row[g.vr], v.threads, v.lds, a, kind, bytes);
+        return launch(ctx, v.stage[stage], g.n_row[g.vr], g.it_row[g.vr], v.threads, v.lds, a, kind, bytes);
     }
     return launch(ctx, k->row_other[mode], g.n_row[0], g.it_row[0], k->row0_threads, k->row0_lds, a, kind, bytes);
 }
@@ -624,7 +645,7 @@ static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, 
     const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
     const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
     return launch(ctx, cv.fn[axis - 1][mode], n, it, cv.threads, cv.lds, a, kind,
-                  2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g));
+                  2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g), cv.tiles);
 }
 
 // k-space kinetic pass of a group (between the forward x pass and the row epilogue).
@@ -702,6 +723,17 @@ static int refresh_T(swf_ctx* ctx) {
 
 // Enqueue one full RK4 step of every solve.
 static int enqueue_step(swf_ctx* ctx) {
+    if (ctx->opt.batched && ctx->opt.chunk > 0 && ctx->P.hv.empty()) {
+        // chunk-major: all four stages of one chunk before the next chunk
+        for (const auto& g : groups(ctx))
+            for (int s = 0; s < 4; ++s) {
+                int r = kinetic_cols(ctx, g, swf::BUF_T, true);
+                if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0, 0);
+                if (r) return r;
+            }
+        HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
+        return SWF_OK;
+    }
     for (int s = 0; s < 4; ++s) {
         int r = bw_stage(ctx, s);
         if (r) return r;
@@ -1158,7 +1190,8 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 for (int m = 0; m < 5; ++m)
                     INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
                 for (int v = 0; v < swf::NVAR; ++v) {
-                    INITCHK(hipFuncSetAttribute(k->row[v].stage, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
+                    for (int st = 0; st < 4; ++st)
+                        INITCHK(hipFuncSetAttribute(k->row[v].stage[st], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
                     for (int a = 0; a < 2; ++a)
                         for (int m = 0; m < 3; ++m)
                             INITCHK(hipFuncSetAttribute(k->col[v].fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col[v].lds));

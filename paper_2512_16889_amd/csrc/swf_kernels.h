@@ -34,6 +34,7 @@ struct PassArgs {
     int h0row;             // 1: the row pass also applies -i H0 / N (dim == 1)
     double t_explicit;     // time of ROW_RHS
     long long ph2;         // ROW_FWDPH: complex offset of exp(i k_j x_j) tables
+    int nitems;            // work items of this launch
 };
 
 // ------------------------------------------------------------------ tile variants
@@ -59,28 +60,75 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int cg_fit(size_t per_comp) { return 4 * per_comp <= LDS_CAP ? 4 : (2 * per_comp <= LDS_CAP ? 2 : 1); }
 
+// waves per SIMD the compiler is asked to fit (0: no hint)
 template <class R, int N, int V> struct RowVar {
-    static constexpr int T = (V == 3) ? half_t<N>() : FftPlan<N>::T;
+    static constexpr int T = FftPlan<N>::T;
     static constexpr int ROWS = imax(1, (V == 2 ? 128 : 256) / T);
     static constexpr int THREADS = T * ROWS;
     using Lay = RowLay<N, ROWS>;
     static constexpr size_t PER_COMP = (size_t)ROWS * Lay::STRIDE * sizeof(cpx<R>);
     static constexpr int CG = V == 0 ? 1 : cg_fit(PER_COMP);
     static constexpr size_t BYTES = CG * PER_COMP;
+    static constexpr bool SEQ = V == 3;
 };
 
 template <class R, int N, int V> struct ColVar {
+    // columns per block: a full 128-byte line (WANT) capped at 512 threads, or
+    // narrower tiles (more, smaller blocks per CU; the host then groups the
+    // tiles of one line on one XCD)
     static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;
-    static constexpr int T = (V >= 2) ? half_t<N>() : FftPlan<N>::T;
-    static constexpr int W = imax(1, imin(V == 2 ? 2 * WANT : WANT, 512 / T));
+    static constexpr int T = FftPlan<N>::T;
+    static constexpr int W0 = imax(1, imin(WANT, 512 / T));
+    static constexpr int W = V == 0 ? W0 : imax(1, (V == 2 ? WANT / 8 : WANT / 4));
     static constexpr int THREADS = T * W;
     static constexpr size_t PER_COMP = (size_t)N * W * sizeof(cpx<R>);
-    static constexpr int CG = (V == 1 || V == 3) ? imin(2, cg_fit(PER_COMP)) : 1;
+    static constexpr int CG = V == 3 ? imin(2, cg_fit(PER_COMP)) : 1;
     static constexpr size_t BYTES = CG * PER_COMP;
+    static constexpr bool SEQ = false;
+    static constexpr int TILES = 1;
 };
 
+
+// Transform the four components of a line: together (shared exchange rounds,
+// more registers live) or one component after another (SEQ: fewer registers,
+// more barriers).
+template <class C, int N, int T, int DIR, int CG, bool SEQ, class Lay>
+__device__ __forceinline__ void fft4(C (&v)[4][N / T], C* lds, int t, int line, const C* tw) {
+    if constexpr (SEQ) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            fft_line<C, N, T, DIR, 1, 1, Lay>(reinterpret_cast<C(&)[1][N / T]>(v[q]), lds, t, line, tw);
+    } else {
+        fft_line<C, N, T, DIR, 4, CG, Lay>(v, lds, t, line, tw);
+    }
+}
+
 // ------------------------------------------------------------------ row pass
-template <class R, int N, int V, int MODE>
+// Global-address-space views of the state arrays (their pointers come from the
+// solve descriptors, so the compiler cannot infer the address space itself and
+// would otherwise emit flat memory instructions).
+template <class T> using gptr = T __attribute__((address_space(1)))*;
+template <class T> __device__ __forceinline__ gptr<T> glob(T* p) { return (gptr<T>)p; }
+// complex numbers cross the global address space as native clang vectors
+template <class R> using nv2 = R __attribute__((ext_vector_type(2)));
+template <class C> __device__ __forceinline__ C gload(gptr<const nv2<decltype(C::x)>> p, long long i) {
+    const nv2<decltype(C::x)> v = p[i];
+    return cmake<C>(v.x, v.y);
+}
+template <class C> __device__ __forceinline__ void gstore(gptr<nv2<decltype(C::x)>> p, long long i, C c) {
+    nv2<decltype(C::x)> v;
+    v.x = c.x;
+    v.y = c.y;
+    p[i] = v;
+}
+template <class R> __device__ __forceinline__ gptr<const nv2<R>> cview(const void* p) {
+    return (gptr<const nv2<R>>)(reinterpret_cast<const nv2<R>*>(p));
+}
+template <class R> __device__ __forceinline__ gptr<nv2<R>> wview(void* p) {
+    return (gptr<nv2<R>>)(reinterpret_cast<nv2<R>*>(p));
+}
+
+template <class R, int N, int V, int MODE, int STAGE>
 __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArgs a) {
     using C = cpx<R>;
     using VC = RowVar<R, N, V>;
@@ -96,6 +144,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
     __shared__ long long sh_tab[MAX_TERMS];
     __shared__ C sh_wc[4];
     __shared__ C sh_phyz[ROWS];
+    __shared__ C tw[N];
 
     const int tid = threadIdx.x;
     const int t = tid % T;
@@ -108,45 +157,49 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
     const int rowc = act ? row : 0;
     const long long base = (long long)rowc * N;
     const long long ns = S->nsites;
-    const C* __restrict__ tw = reinterpret_cast<const C*>(a.ctab) + S->tw[0];
-    const C* __restrict__ ctab = reinterpret_cast<const C*>(a.ctab);
-    const R* __restrict__ rtab = reinterpret_cast<const R*>(a.rtab);
+    // twiddle table in LDS: the first twiddle read comes after the first
+    // exchange's barriers, so no extra barrier is needed here
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[0] + i);
     const int n0 = S->n[0], n1 = S->n[1];
     const int yy = rowc % n1, zz = rowc / n1;
-    C v[4][E];
 
-    if constexpr (MODE == ROW_FWD || MODE == ROW_FWDPH) {
-        const C* __restrict__ src = reinterpret_cast<const C*>(S->buf[a.src]);
+    auto load = [&](int role, C (&w)[4][E]) {
+        gptr<const nv2<R>> p = cview<R>(S->buf[role]) + base + t;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[q][m] = src[q * ns + base + t + T * m];
+            for (int m = 0; m < E; ++m) w[q][m] = gload<C>(p, q * ns + T * m);
+    };
+    auto store = [&](int role, const C (&w)[4][E]) {
+        if (!act) return;
+        gptr<nv2<R>> p = wview<R>(S->buf[role]) + base + t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore<C>(p, q * ns + T * m, w[q][m]);
+    };
+
+    C v[4][E];
+    if constexpr (MODE == ROW_FWD || MODE == ROW_FWDPH) {
+        load(a.src, v);
         if constexpr (MODE == ROW_FWDPH) {
-            const C* ph = ctab + a.ph2;
-            const C pyz = cmul(ph[n0 + yy], ph[n0 + n1 + zz]);
+            const long long ph = a.ph2;
+            const C pyz = cmul(gload<C>(ctab, ph + n0 + yy), gload<C>(ctab, ph + n0 + n1 + zz));
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                const C p = cmul(ph[t + T * m], pyz);
+                const C p = cmul(gload<C>(ctab, ph + t + T * m), pyz);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q][m] = cmul(v[q][m], p);
             }
         }
-        fft_line<C, N, T, -1, 4, CG, Lay>(v, lds, t, line, tw);
-        if (act) {
-            C* __restrict__ dst = reinterpret_cast<C*>(S->buf[a.dst]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int m = 0; m < E; ++m) dst[q * ns + base + t + T * m] = v[q][m];
-        }
+        fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
+        store(a.dst, v);
         return;
     } else {
         // ---- inverse transform of the k-space buffer (optionally after -i H0 / N)
-        const C* __restrict__ tb = reinterpret_cast<const C*>(S->buf[BUF_T]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int m = 0; m < E; ++m) v[q][m] = tb[q * ns + base + t + T * m];
+        load(BUF_T, v);
         if (a.h0row) {
             const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], s = (R)S->inv_n;
             const double dk = S->dk[0];
@@ -156,15 +209,9 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
             }
         }
-        fft_line<C, N, T, +1, 4, CG, Lay>(v, lds, t, line, tw);
+        fft4<C, N, T, +1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
         if constexpr (MODE == ROW_INV) {
-            if (act) {
-                C* __restrict__ dst = reinterpret_cast<C*>(S->buf[a.dst]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int m = 0; m < E; ++m) dst[q * ns + base + t + T * m] = v[q][m];
-            }
+            store(a.dst, v);
             return;
         } else {
             // ---- stage epilogue: k = K - i V(t_i) (y_i + psi_b(t_i))
@@ -172,9 +219,8 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
             if constexpr (MODE == ROW_RHS) {
                 ts = a.t_explicit;
             } else {
-                const int n = *a.step;
-                const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
-                ts = a.t_out - (double)n * a.dt - cst * a.dt;
+                constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
+                ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
             }
             const int nterm = S->nterm;
             for (int j = t; j < nterm; j += T) {
@@ -192,102 +238,102 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 const double wr = S->w[2 * q], wi = S->w[2 * q + 1];
                 sh_wc[q] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
             }
-            if (t == 0) {
-                const C* ph = ctab + S->ph;
-                sh_phyz[line] = cmul(ph[n0 + yy], ph[n0 + n1 + zz]);
-            }
+            if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
+            // state loads are independent of the barrier below: issue them first
+            C yi[4][E];
+            load(MODE == ROW_RHS ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
             __syncthreads();
-            const C* __restrict__ phx = ctab + S->ph;
-            const C wc0 = sh_wc[0], wc1 = sh_wc[1], wc2 = sh_wc[2], wc3 = sh_wc[3];
+            // field A_mu on this line's points
+            R A[4][E];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int m = 0; m < E; ++m) A[mu][m] = (R)0;
+#pragma unroll
+            for (int j = 0; j < MAX_TERMS; ++j) {
+                if (j < nterm) {
+                    const R fyz = sh_fyz[line][j];
+                    gptr<const R> tab = rtab + sh_tab[j] + t;
+                    const int mu = sh_mu[j];
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const R f = fyz * tab[T * m];
+                        A[0][m] += mu == 0 ? f : (R)0;
+                        A[1][m] += mu == 1 ? f : (R)0;
+                        A[2][m] += mu == 2 ? f : (R)0;
+                        A[3][m] += mu == 3 ? f : (R)0;
+                    }
+                }
+            }
+            const long long phx = S->ph + t;
+            const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
             const C phyz = sh_phyz[line];
-            const R h = (R)(-a.dt);
-            const R h2 = (R)(-0.5 * a.dt), h3 = (R)(-a.dt / 3.0), h6 = (R)(-a.dt / 6.0);
-            C* __restrict__ Y = reinterpret_cast<C*>(S->buf[BUF_Y]);
-            C* __restrict__ ACC = reinterpret_cast<C*>(S->buf[BUF_ACC]);
-            C* __restrict__ YS = reinterpret_cast<C*>(S->buf[BUF_YS]);
-            const C* __restrict__ YIN = reinterpret_cast<const C*>(S->buf[MODE == ROW_RHS ? a.src : (a.stage == 0 ? BUF_Y : BUF_YS)]);
-            const long long mask = S->mask;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                const int x = t + T * m;
-                const long long o = base + x;
-                R A0 = 0, A1 = 0, A2 = 0, A3 = 0;
-                for (int j = 0; j < nterm; ++j) {
-                    const R f = sh_fyz[line][j] * rtab[sh_tab[j] + x];
-                    const int mu = sh_mu[j];
-                    A0 += mu == 0 ? f : (R)0;
-                    A1 += mu == 1 ? f : (R)0;
-                    A2 += mu == 2 ? f : (R)0;
-                    A3 += mu == 3 ? f : (R)0;
-                }
-                const C ph = cmul(phx[x], phyz);
-                C s[4], yi[4];
+                const C ph = cmul(gload<C>(ctab, phx + T * m), phyz);
+                C sv[4], vs[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) yi[q] = YIN[q * ns + o];
-                s[0] = cadd(yi[0], cmul(wc0, ph));
-                s[1] = cadd(yi[1], cmul(wc1, ph));
-                s[2] = cadd(yi[2], cmul(wc2, ph));
-                s[3] = cadd(yi[3], cmul(wc3, ph));
-                C vs[4];
-                apply_pot(s, vs, A0, A1, A2, A3);
-                C k[4];
+                for (int q = 0; q < 4; ++q) sv[q] = cadd(yi[q][m], cmul(wc[q], ph));
+                apply_pot(sv, vs, A[0][m], A[1][m], A[2][m], A[3][m]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) k[q] = cadd(v[q][m], cmul_mi(vs[q]));
-                if constexpr (MODE == ROW_RHS) {
-                    if (act) {
-                        C* dst = reinterpret_cast<C*>(S->buf[a.dst]);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) dst[q * ns + o] = k[q];
-                    }
-                } else {
-                    if (a.stage == 0) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const C acc = cadd(yi[q], cscale(k[q], h6));
-                            const C yn = cadd(yi[q], cscale(k[q], h2));
-                            if (act) {
-                                ACC[q * ns + o] = acc;
-                                YS[q * ns + o] = yn;
-                            }
-                            v[q][m] = yn;
-                        }
-                    } else if (a.stage < 3) {
-                        const R hc = a.stage == 1 ? h2 : h;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const C y0 = Y[q * ns + o];
-                            const C acc = cadd(ACC[q * ns + o], cscale(k[q], h3));
-                            const C yn = cadd(y0, cscale(k[q], hc));
-                            if (act) {
-                                ACC[q * ns + o] = acc;
-                                YS[q * ns + o] = yn;
-                            }
-                            v[q][m] = yn;
-                        }
-                    } else {
-                        R mk = (R)1;
-                        if (mask >= 0)
-                            mk = rtab[mask + x] * rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            C yn = cadd(ACC[q * ns + o], cscale(k[q], h6));
-                            if (mask >= 0) yn = cscale(yn, mk);
-                            if (act) Y[q * ns + o] = yn;
-                            v[q][m] = yn;
-                        }
-                    }
-                }
+                for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));   // v = k
             }
-            if constexpr (MODE == ROW_STAGE) {
-                // forward x transform of the next stage's input
-                fft_line<C, N, T, -1, 4, CG, Lay>(v, lds, t, line, tw);
-                if (act) {
-                    C* __restrict__ tbw = reinterpret_cast<C*>(S->buf[BUF_T]);
+            if constexpr (MODE == ROW_RHS) {
+                store(a.dst, v);
+                return;
+            } else {
+                const R h = (R)(-a.dt);
+                const R h2 = (R)(-0.5 * a.dt), h3 = (R)(-a.dt / 3.0), h6 = (R)(-a.dt / 6.0);
+                if constexpr (STAGE == 0) {
+                    // y_1 = y: acc = y + h/6 k1, y_2 = y + h/2 k1
+                    C acc[4][E];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int m = 0; m < E; ++m) tbw[q * ns + base + t + T * m] = v[q][m];
+                        for (int m = 0; m < E; ++m) {
+                            acc[q][m] = cadd(yi[q][m], cscale(v[q][m], h6));
+                            v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));
+                        }
+                    store(BUF_ACC, acc);
+                    store(BUF_YS, v);
+                } else if constexpr (STAGE == 1 || STAGE == 2) {
+                    // acc += h/3 k, y_{i+1} = y + c h k
+                    const R hc = STAGE == 1 ? h2 : h;
+                    C y0[4][E], acc[4][E];
+                    load(BUF_Y, y0);
+                    load(BUF_ACC, acc);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int m = 0; m < E; ++m) {
+                            acc[q][m] = cadd(acc[q][m], cscale(v[q][m], h3));
+                            v[q][m] = cadd(y0[q][m], cscale(v[q][m], hc));
+                        }
+                    store(BUF_ACC, acc);
+                    store(BUF_YS, v);
+                } else {
+                    // y_{n+1} = acc + h/6 k4, then the boundary mask
+                    C acc[4][E];
+                    load(BUF_ACC, acc);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int m = 0; m < E; ++m) v[q][m] = cadd(acc[q][m], cscale(v[q][m], h6));
+                    const long long mask = S->mask;
+                    if (mask >= 0) {
+                        const R myz = rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
+#pragma unroll
+                        for (int m = 0; m < E; ++m) {
+                            const R mk = rtab[mask + t + T * m] * myz;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) v[q][m] = cscale(v[q][m], mk);
+                        }
+                    }
+                    store(BUF_Y, v);
                 }
+                // forward x transform of the next stage's input
+                fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
+                store(BUF_T, v);
             }
         }
     }
@@ -302,6 +348,7 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
     constexpr int W = VC::W;
     constexpr int CG = VC::CG;
     constexpr int E = N / T;
+    constexpr int TPB = VC::TILES;
     using Lay = ColLay<N, W>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
@@ -309,55 +356,97 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
     const int tid = threadIdx.x;
     const int xl = tid % W;
     const int t = tid / W;
-    const int2 it = a.items[blockIdx.x];
-    const SolveDev* __restrict__ S = a.solves + it.x;
-    const int n0 = S->n[0], n1 = S->n[1];
-    const int ntx = (n0 + W - 1) / W;
-    const int xt = it.y % ntx;
-    const int other = it.y / ntx;
-    const int x = xt * W + xl;
-    const bool act = x < n0;
-    const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
-    const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
-    const long long base = obase + (act ? x : 0);
-    const long long ns = S->nsites;
-    C* __restrict__ buf = reinterpret_cast<C*>(S->buf[a.dst]);
-    const C* __restrict__ tw = reinterpret_cast<const C*>(a.ctab) + S->tw[AXIS];
-    C v[4][E];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[q][m] = buf[q * ns + base + (long long)(t + T * m) * stride];
-    if constexpr (MODE == COL_FWD || MODE == COL_H0) fft_line<C, N, T, -1, 4, CG, Lay>(v, lds, t, xl, tw);
-    if constexpr (MODE == COL_H0) {
-        const R s = (R)S->inv_n;
-        const R Kx = (R)(S->dk[0] * kindex(act ? x : 0, n0));
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int idx = t + T * m;
-            R Ky, Kz;
-            if constexpr (AXIS == 1) {
-                Ky = (R)(S->dk[1] * kindex(idx, N));
-                Kz = (R)S->kap[2];
-            } else {
-                Ky = (R)(S->dk[1] * kindex(other, n1));
-                Kz = (R)(S->dk[2] * kindex(idx, N));
-            }
-            apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
-        }
-    }
-    if constexpr (MODE == COL_INV || MODE == COL_H0) fft_line<C, N, T, +1, 4, CG, Lay>(v, lds, t, xl, tw);
-    if (act) {
+
+    // One tile = W adjacent columns of one solve, one fixed other-axis index.
+    struct Tile {
+        const SolveDev* S;
+        C* buf;
+        long long base, stride, ns;
+        int x, other, n0, n1;
+        bool act;
+    };
+    auto decode = [&](int item) {
+        Tile c;
+        const int2 it = a.items[item];
+        c.S = a.solves + it.x;
+        c.n0 = c.S->n[0];
+        c.n1 = c.S->n[1];
+        const int ntx = (c.n0 + W - 1) / W;
+        c.other = it.y / ntx;
+        c.x = (it.y % ntx) * W + xl;
+        c.act = c.x < c.n0;
+        c.stride = AXIS == 1 ? (long long)c.n0 : (long long)c.n0 * c.n1;
+        const long long obase = AXIS == 1 ? (long long)c.other * c.n0 * c.n1 : (long long)c.other * c.n0;
+        c.base = obase + (c.act ? c.x : 0);
+        c.ns = c.S->nsites;
+        c.buf = reinterpret_cast<C*>(c.S->buf[a.dst]);
+        return c;
+    };
+    auto load = [&](const Tile& c, C (&w)[4][E]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) buf[q * ns + base + (long long)(t + T * m) * stride] = v[q][m];
+            for (int m = 0; m < E; ++m) w[q][m] = c.buf[q * c.ns + c.base + (long long)(t + T * m) * c.stride];
+    };
+
+    const int first = blockIdx.x * TPB;
+    Tile cur = decode(first);
+    __shared__ C tw[N];
+    {
+        const C* __restrict__ twg = reinterpret_cast<const C*>(a.ctab) + cur.S->tw[AXIS];
+        for (int i = tid; i < N; i += VC::THREADS) tw[i] = twg[i];
+    }
+    C v[4][E];
+    load(cur, v);
+#pragma unroll
+    for (int k = 0; k < TPB; ++k) {
+        // software pipeline: the next tile's loads are in flight while this
+        // tile is transformed
+        const bool has_next = (k + 1 < TPB) && (first + k + 1 < a.nitems);
+        Tile nxt;
+        C vn[4][E];
+        if (has_next) {
+            nxt = decode(first + k + 1);
+            load(nxt, vn);
+        }
+        if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, xl, tw);
+        if constexpr (MODE == COL_H0) {
+            const SolveDev* S = cur.S;
+            const R s = (R)S->inv_n;
+            const R Kx = (R)(S->dk[0] * kindex(cur.act ? cur.x : 0, cur.n0));
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int idx = t + T * m;
+                R Ky, Kz;
+                if constexpr (AXIS == 1) {
+                    Ky = (R)(S->dk[1] * kindex(idx, N));
+                    Kz = (R)S->kap[2];
+                } else {
+                    Ky = (R)(S->dk[1] * kindex(cur.other, cur.n1));
+                    Kz = (R)(S->dk[2] * kindex(idx, N));
+                }
+                apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+            }
+        }
+        if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay>(v, lds, t, xl, tw);
+        if (cur.act) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int m = 0; m < E; ++m) cur.buf[q * cur.ns + cur.base + (long long)(t + T * m) * cur.stride] = v[q][m];
+        }
+        if (!has_next) break;
+        cur = nxt;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[q][m] = vn[q][m];
     }
 }
 
 // Kernel table of one (precision, N) instantiation.
-struct RowVariant { const void* stage; int threads, rows; size_t lds; };
-struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
+struct RowVariant { const void* stage[4]; int threads, rows; size_t lds; };
+struct ColVariant { const void* fn[2][3]; int threads, w, tiles; size_t lds; };
 struct SizeKernels {
     int nvar;
     RowVariant row[NVAR];          // the RK4 stage pass, by variant
@@ -370,7 +459,9 @@ struct SizeKernels {
 template <class R, int N, int V>
 RowVariant make_row_variant() {
     using VC = RowVar<R, N, V>;
-    return RowVariant{(const void*)row_kernel<R, N, V, ROW_STAGE>, VC::THREADS, VC::ROWS, VC::BYTES};
+    return RowVariant{{(const void*)row_kernel<R, N, V, ROW_STAGE, 0>, (const void*)row_kernel<R, N, V, ROW_STAGE, 1>,
+                       (const void*)row_kernel<R, N, V, ROW_STAGE, 2>, (const void*)row_kernel<R, N, V, ROW_STAGE, 3>},
+                      VC::THREADS, VC::ROWS, VC::BYTES};
 }
 template <class R, int N, int V>
 ColVariant make_col_variant() {
@@ -384,6 +475,7 @@ ColVariant make_col_variant() {
     c.fn[1][COL_H0] = (const void*)col_kernel<R, N, V, COL_H0, 2>;
     c.threads = VC::THREADS;
     c.w = VC::W;
+    c.tiles = VC::TILES;
     c.lds = VC::BYTES;
     return c;
 }
@@ -407,11 +499,11 @@ SizeKernels make_size_kernels() {
             k.col[v] = k.col[0];
         }
     }
-    k.row_other[ROW_FWD] = (const void*)row_kernel<R, N, 0, ROW_FWD>;
-    k.row_other[ROW_STAGE] = (const void*)row_kernel<R, N, 0, ROW_STAGE>;
-    k.row_other[ROW_INV] = (const void*)row_kernel<R, N, 0, ROW_INV>;
-    k.row_other[ROW_RHS] = (const void*)row_kernel<R, N, 0, ROW_RHS>;
-    k.row_other[ROW_FWDPH] = (const void*)row_kernel<R, N, 0, ROW_FWDPH>;
+    k.row_other[ROW_FWD] = (const void*)row_kernel<R, N, 0, ROW_FWD, 0>;
+    k.row_other[ROW_STAGE] = (const void*)row_kernel<R, N, 0, ROW_STAGE, 0>;
+    k.row_other[ROW_INV] = (const void*)row_kernel<R, N, 0, ROW_INV, 0>;
+    k.row_other[ROW_RHS] = (const void*)row_kernel<R, N, 0, ROW_RHS, 0>;
+    k.row_other[ROW_FWDPH] = (const void*)row_kernel<R, N, 0, ROW_FWDPH, 0>;
     k.row0_threads = RowVar<R, N, 0>::THREADS;
     k.row0_rows = RowVar<R, N, 0>::ROWS;
     k.row0_lds = RowVar<R, N, 0>::BYTES;
