@@ -38,11 +38,18 @@ def projector_field(sv, sign: int):
 
 
 def projected_overlap(sa, psi_a, psi_b, sign: int):
-    """dV/N sum_k FFT(psi_a)^dagger Pi_sign(k) FFT(psi_b), Pi on sa's lattice."""
+    """dV/N sum_k FFT(psi_a)^dagger Pi_sign(k) FFT(psi_b), Pi on sa's lattice.
+
+    Pi is an orthogonal projector (Hermitian, Pi^2 = Pi), so the quadratic form
+    equals (Pi a)^dagger (Pi b); that form is used because the probabilities of
+    interest are exponentially small next to (psi|psi): the expanded form
+    1/2 (|a|^2 - a^dag H0 a / E) would cancel to a relative error of order
+    eps (psi|psi)/P, the projected form keeps it at eps sqrt((psi|psi)/P)."""
     lat = sa.lat
-    ak = lat.fft(psi_a)
-    bk = lat.fft(psi_b)
-    return lat.dV / lat.N * np.sum(np.conj(ak) * apply(projector_field(sa, sign), bk))
+    P = projector_field(sa, sign)
+    pa = apply(P, lat.fft(psi_a))
+    pb = pa if psi_b is psi_a else apply(P, lat.fft(psi_b))
+    return lat.dV / lat.N * np.sum(np.conj(pa) * pb)
 
 
 def marginal(sv, psi_s):
@@ -96,5 +103,5 @@ def marginal_in_uniform_field(sv, psi_full, A_cov):
         (4, 4) + lat.shape) + dirac.BETA.reshape((4, 4) + (1,) * lat.dim)
     E = np.sqrt(1.0 + sum(k ** 2 for k in kin))
     P = 0.5 * (dirac.I4.reshape((4, 4) + (1,) * lat.dim) + sign * H / E[None, None])
-    pk = lat.fft(psi_full)
-    return float(np.real(lat.dV / lat.N * np.sum(np.conj(pk) * apply(P, pk))))
+    pk = apply(P, lat.fft(psi_full))
+    return float(np.real(lat.dV / lat.N * np.sum(np.conj(pk) * pk)))

@@ -73,7 +73,10 @@ __device__ __forceinline__ void site_k(const SolveDev* S, int x, int y, int z, d
     Kz = S->dim >= 3 ? S->dk[2] * kindex(z, S->n[2]) : S->kap[2];
 }
 
-// sum_k A(k)^dag Pi_sign(K) B(k), K the full momentum of A's lattice.
+// sum_k (Pi_sign(K) A(k))^dag (Pi_sign(K) B(k)), K the full momentum of A's
+// lattice.  Equal to A^dag Pi B (Pi is an orthogonal projector); the projected
+// vectors are formed first because the probabilities are exponentially small
+// next to |A|^2 and the expanded form would cancel catastrophically.
 template <class R>
 __global__ void __launch_bounds__(RED_THREADS) kspace_proj_kernel(RedArgs a) {
     using C = cpx<R>;
@@ -81,6 +84,7 @@ __global__ void __launch_bounds__(RED_THREADS) kspace_proj_kernel(RedArgs a) {
     const SolveDev* SB = a.solves + a.sb;
     const C* A = reinterpret_cast<const C*>(SA->buf[a.ra]);
     const C* B = reinterpret_cast<const C*>(SB->buf[a.rb]);
+    const bool same = (A == B);
     const long long ns = SA->nsites;
     double2 acc[1] = {d2(0, 0)};
     for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
@@ -88,19 +92,27 @@ __global__ void __launch_bounds__(RED_THREADS) kspace_proj_kernel(RedArgs a) {
         site_xyz(i, SA, x, y, z);
         double Kx, Ky, Kz;
         site_k(SA, x, y, z, Kx, Ky, Kz);
-        const double E = sqrt(1.0 + Kx * Kx + Ky * Ky + Kz * Kz);
-        double2 pa[4], pb[4], hb[4];
+        const double sg = a.sign / sqrt(1.0 + Kx * Kx + Ky * Ky + Kz * Kz);
+        double2 pa[4], pb[4], h[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            pa[q] = todbl(A[q * ns + i]);
-            pb[q] = todbl(B[q * ns + i]);
+        for (int q = 0; q < 4; ++q) pa[q] = todbl(A[q * ns + i]);
+        h0d(pa, h, Kx, Ky, Kz);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pa[q] = dsc(dadd(pa[q], dsc(h[q], sg)), 0.5);
+        if (same) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pb[q] = pa[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pb[q] = todbl(B[q * ns + i]);
+            h0d(pb, h, Kx, Ky, Kz);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pb[q] = dsc(dadd(pb[q], dsc(h[q], sg)), 0.5);
         }
-        h0d(pb, hb, Kx, Ky, Kz);
-        const double sg = a.sign / E;
         double2 s = d2(0, 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s = dadd(s, dcmul(pa[q], dadd(pb[q], dsc(hb[q], sg))));
-        acc[0] = dadd(acc[0], dsc(s, 0.5));
+        for (int q = 0; q < 4; ++q) s = dadd(s, dcmul(pa[q], pb[q]));
+        acc[0] = dadd(acc[0], s);
     }
     block_sum_store<1>(acc, a.out);
 }

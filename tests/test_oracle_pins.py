@@ -189,3 +189,26 @@ def test_time_only_mode_matches_dop853():
     c = sol.y[:, -1].view(complex)
     n_ref = float(np.real(c.conj() @ dirac.projector([px, pp, 0.0], -1) @ c))
     assert P == pytest.approx(n_ref, rel=1e-7)
+
+
+def test_marginal_resolves_tiny_negative_energy_content():
+    # psi~(k) = a(k) u(k) + b(k) v(k) with |b|^2 / |a|^2 ~ 1e-12: the electron
+    # marginal must return dV/N sum |b|^2 (orthonormal eigenvectors) to high
+    # relative accuracy although (psi|psi) is 1e12 times larger.
+    n, L = 32, 40.0
+    prob = W.Problem("t", [W.Grid(1, [n, 1, 1], [L, 1, 1])], [[]], [W.Solve(0, 1, [0.0, 0.3, 0.0])],
+                     W.Window(-1.0, 1.0, 0.1))
+    sv = SWFSolve(prob, 0)
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    b = 1e-6 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    psik = np.zeros((4, n), dtype=complex)
+    for i in range(n):
+        K = [sv.kfull[0][i], sv.kfull[1][i], sv.kfull[2][i]]
+        w, V = np.linalg.eigh(dirac.hamiltonian0(K))      # ascending: two negative, two positive
+        psik[:, i] = a[i] * V[:, 3] + b[i] * V[:, 0]
+    psi = np.fft.ifft(psik, axis=1)
+    want = sv.lat.dV / n * np.sum(np.abs(b) ** 2)
+    total = sv.lat.dV / n * np.sum(np.abs(a) ** 2 + np.abs(b) ** 2)
+    assert total / want > 1e11
+    assert ob.marginal(sv, psi) == pytest.approx(want, rel=1e-6)
