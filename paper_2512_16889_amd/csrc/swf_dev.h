@@ -95,9 +95,26 @@ SWF_PLAN(160, 8, 5, 4, 4, 2)
 SWF_PLAN(320, 16, 5, 4, 4, 4)
 #undef SWF_PLAN
 
-template <int N> constexpr int plan_stride(int j) {
+// Plans with 4 points per thread (radix 4, a final radix 2 when log2 N is
+// odd): twice the threads per line and half the registers of the default.
+template <int N> struct Plan4;
+#define SWF_PLAN4(N_, ...)                                               \
+    template <> struct Plan4<N_> {                                       \
+        static constexpr int T = N_ / 4;                                 \
+        static constexpr int R[] = {__VA_ARGS__};                        \
+        static constexpr int NR = sizeof(R) / sizeof(int);               \
+    };
+SWF_PLAN4(64, 4, 4, 4)
+SWF_PLAN4(128, 4, 4, 4, 2)
+SWF_PLAN4(256, 4, 4, 4, 4)
+SWF_PLAN4(512, 4, 4, 4, 4, 2)
+SWF_PLAN4(1024, 4, 4, 4, 4, 4)
+#undef SWF_PLAN4
+template <int N> constexpr bool has_plan4() { return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024; }
+
+template <class P> constexpr int plan_stride(int j) {
     int s = 1;
-    for (int i = 0; i < j; ++i) s *= FftPlan<N>::R[i];
+    for (int i = 0; i < j; ++i) s *= P::R[i];
     return s;
 }
 
@@ -184,10 +201,10 @@ template <int DIR, class C> struct Dft<8, DIR, C> {
 // previous radices) runs butterflies b = t + T*c, c < E/R; input k of butterfly
 // b is point b + k N/R (register c + (E/R) k), output k goes to position
 // (b / NS) NS R + (b % NS) + k NS of the step's output.
-template <class C, int N, int T, int J, int DIR, int NC>
+template <class C, int N, int T, int J, int DIR, int NC, class P>
 __device__ __forceinline__ void fft_step(C (&v)[NC][N / T], int t, const C* __restrict__ tw) {
-    constexpr int R = FftPlan<N>::R[J];
-    constexpr int NS = plan_stride<N>(J);
+    constexpr int R = P::R[J];
+    constexpr int NS = plan_stride<P>(J);
     constexpr int E = N / T;
     constexpr int B = E / R;
 #pragma unroll
@@ -220,11 +237,11 @@ __device__ __forceinline__ void fft_step(C (&v)[NC][N / T], int t, const C* __re
 // Exchange the outputs of step J-1 into the inputs of step J through LDS,
 // CG components at a time.  Lay::addr(q, line, idx) is the LDS slot of point
 // idx of component q (within the group) of this thread's line.
-template <class C, int N, int T, int J, int NC, int CG, class Lay>
+template <class C, int N, int T, int J, int NC, int CG, class Lay, class P>
 __device__ __forceinline__ void fft_exchange(C (&v)[NC][N / T], C* lds, int t, int line) {
-    constexpr int Rp = FftPlan<N>::R[J - 1];
-    constexpr int NSp = plan_stride<N>(J - 1);
-    constexpr int R = FftPlan<N>::R[J];
+    constexpr int Rp = P::R[J - 1];
+    constexpr int NSp = plan_stride<P>(J - 1);
+    constexpr int R = P::R[J];
     constexpr int E = N / T;
     constexpr int Bp = E / Rp;
     constexpr int B = E / R;
@@ -254,22 +271,23 @@ __device__ __forceinline__ void fft_exchange(C (&v)[NC][N / T], C* lds, int t, i
     }
 }
 
-template <class C, int N, int T, int J, int DIR, int NC, int CG, class Lay>
+template <class C, int N, int T, int J, int DIR, int NC, int CG, class Lay, class P>
 struct FftRun {
     static __device__ __forceinline__ void run(C (&v)[NC][N / T], C* lds, int t, int line, const C* tw) {
-        if constexpr (J < FftPlan<N>::NR) {
-            if constexpr (J > 0) fft_exchange<C, N, T, J, NC, CG, Lay>(v, lds, t, line);
-            fft_step<C, N, T, J, DIR, NC>(v, t, tw);
-            FftRun<C, N, T, J + 1, DIR, NC, CG, Lay>::run(v, lds, t, line, tw);
+        if constexpr (J < P::NR) {
+            if constexpr (J > 0) fft_exchange<C, N, T, J, NC, CG, Lay, P>(v, lds, t, line);
+            fft_step<C, N, T, J, DIR, NC, P>(v, t, tw);
+            FftRun<C, N, T, J + 1, DIR, NC, CG, Lay, P>::run(v, lds, t, line, tw);
         }
     }
 };
 
 // Unnormalised transform of NC components along one line, DIR = -1 forward
-// (numpy sign), +1 inverse.  tw[m] = exp(-2 pi i m / N).
-template <class C, int N, int T, int DIR, int NC, int CG, class Lay>
+// (numpy sign), +1 inverse.  tw[m] = exp(-2 pi i m / N).  P gives the radix
+// list; every radix must divide N/T and T must divide N/radix.
+template <class C, int N, int T, int DIR, int NC, int CG, class Lay, class P = FftPlan<N>>
 __device__ __forceinline__ void fft_line(C (&v)[NC][N / T], C* lds, int t, int line, const C* tw) {
-    FftRun<C, N, T, 0, DIR, NC, CG, Lay>::run(v, lds, t, line, tw);
+    FftRun<C, N, T, 0, DIR, NC, CG, Lay, P>::run(v, lds, t, line, tw);
 }
 
 // LDS layouts.  Row passes: lanes run along the line (t fastest), one padded

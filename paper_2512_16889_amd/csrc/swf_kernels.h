@@ -43,12 +43,15 @@ struct PassArgs {
 //   row pass: T threads per x-line, ROWS lines per block, CG components per
 //             LDS exchange round;
 //   column pass: T threads per line, W adjacent x-columns per block, CG.
-template <int N, int T> constexpr bool plan_ok() {
+template <int N, int T, class P = FftPlan<N>> constexpr bool plan_ok() {
     if (T < 1 || N % T) return false;
-    for (int j = 0; j < FftPlan<N>::NR; ++j)
-        if ((N / FftPlan<N>::R[j]) % T || (N / T) % FftPlan<N>::R[j]) return false;
+    for (int j = 0; j < P::NR; ++j)
+        if ((N / P::R[j]) % T || (N / T) % P::R[j]) return false;
     return true;
 }
+// the plan of a variant: the default one, or the 4-points-per-thread one
+template <int N, bool FOUR> struct PlanSel { using type = FftPlan<N>; };
+template <int N> struct PlanSel<N, true> { using type = Plan4<N>; };
 template <int N> constexpr int half_t() {
     constexpr int T = FftPlan<N>::T;
     return (T % 2 == 0 && 2 * N / T <= 16 && plan_ok<N, T / 2>()) ? T / 2 : T;
@@ -62,44 +65,50 @@ constexpr int cg_fit(size_t per_comp) { return 4 * per_comp <= LDS_CAP ? 4 : (2 
 
 // waves per SIMD the compiler is asked to fit (0: no hint)
 template <class R, int N, int V> struct RowVar {
-    static constexpr int T = FftPlan<N>::T;
+    static constexpr bool FOUR = V == 3 && has_plan4<N>();
+    using PL = typename PlanSel<N, FOUR>::type;
+    static constexpr int T = PL::T;
     static constexpr int ROWS = imax(1, (V == 2 ? 128 : 256) / T);
     static constexpr int THREADS = T * ROWS;
     using Lay = RowLay<N, ROWS>;
     static constexpr size_t PER_COMP = (size_t)ROWS * Lay::STRIDE * sizeof(cpx<R>);
     static constexpr int CG = V == 0 ? 1 : cg_fit(PER_COMP);
     static constexpr size_t BYTES = CG * PER_COMP;
-    static constexpr bool SEQ = V == 3;
+    static constexpr bool SEQ = false;
+    static_assert(plan_ok<N, T, PL>(), "row variant violates the FFT plan constraints");
 };
 
 template <class R, int N, int V> struct ColVar {
     // columns per block: a full 128-byte line (WANT) capped at 512 threads, or
     // narrower tiles (more, smaller blocks per CU; the host then groups the
-    // tiles of one line on one XCD)
+    // tiles of one line on one XCD); v2 uses the 4-points-per-thread plan
     static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;
-    static constexpr int T = FftPlan<N>::T;
+    static constexpr bool FOUR = V == 2 && has_plan4<N>();
+    using PL = typename PlanSel<N, FOUR>::type;
+    static constexpr int T = PL::T;
     static constexpr int W0 = imax(1, imin(WANT, 512 / T));
-    static constexpr int W = V == 0 ? W0 : imax(1, (V == 2 ? WANT / 8 : WANT / 4));
+    static constexpr int W = (V == 0 || V == 2) ? W0 : imax(1, WANT / 4);
     static constexpr int THREADS = T * W;
     static constexpr size_t PER_COMP = (size_t)N * W * sizeof(cpx<R>);
     static constexpr int CG = V == 3 ? imin(2, cg_fit(PER_COMP)) : 1;
     static constexpr size_t BYTES = CG * PER_COMP;
     static constexpr bool SEQ = false;
     static constexpr int TILES = 1;
+    static_assert(plan_ok<N, T, PL>(), "column variant violates the FFT plan constraints");
 };
 
 
 // Transform the four components of a line: together (shared exchange rounds,
 // more registers live) or one component after another (SEQ: fewer registers,
 // more barriers).
-template <class C, int N, int T, int DIR, int CG, bool SEQ, class Lay>
+template <class C, int N, int T, int DIR, int CG, bool SEQ, class Lay, class P>
 __device__ __forceinline__ void fft4(C (&v)[4][N / T], C* lds, int t, int line, const C* tw) {
     if constexpr (SEQ) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            fft_line<C, N, T, DIR, 1, 1, Lay>(reinterpret_cast<C(&)[1][N / T]>(v[q]), lds, t, line, tw);
+            fft_line<C, N, T, DIR, 1, 1, Lay, P>(reinterpret_cast<C(&)[1][N / T]>(v[q]), lds, t, line, tw);
     } else {
-        fft_line<C, N, T, DIR, 4, CG, Lay>(v, lds, t, line, tw);
+        fft_line<C, N, T, DIR, 4, CG, Lay, P>(v, lds, t, line, tw);
     }
 }
 
@@ -194,7 +203,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 for (int q = 0; q < 4; ++q) v[q][m] = cmul(v[q][m], p);
             }
         }
-        fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
+        fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
         store(a.dst, v);
         return;
     } else {
@@ -209,7 +218,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
             }
         }
-        fft4<C, N, T, +1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
+        fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
         if constexpr (MODE == ROW_INV) {
             store(a.dst, v);
             return;
@@ -332,7 +341,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                     store(BUF_Y, v);
                 }
                 // forward x transform of the next stage's input
-                fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, line, tw);
+                fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
                 store(BUF_T, v);
             }
         }
@@ -409,7 +418,7 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
             nxt = decode(first + k + 1);
             load(nxt, vn);
         }
-        if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay>(v, lds, t, xl, tw);
+        if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
         if constexpr (MODE == COL_H0) {
             const SolveDev* S = cur.S;
             const R s = (R)S->inv_n;
@@ -428,7 +437,7 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
                 apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
             }
         }
-        if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay>(v, lds, t, xl, tw);
+        if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
         if (cur.act) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
