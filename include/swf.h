@@ -110,6 +110,8 @@ typedef struct {
                                (0 = all solves of a grid size).  Without BW vertices a
                                time step then runs all passes of one chunk before the
                                next, so a chunk's arrays can stay in the on-die cache  */
+    int force_variant;      /* > 0: use tile variant force_variant - 1 (0..3) for every pass
+                               (testing); 0: the autotuned or the default variant       */
 } swf_options;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */

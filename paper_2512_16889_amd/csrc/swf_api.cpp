@@ -1200,7 +1200,11 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     ctx->kvalid.assign(P.solves.size(), 0);
     ctx->bw_done.assign(P.hv.size(), 0);
     ctx->bw_cache.assign(6 * P.hv.size(), cd(0));
-    if (opt->tune) {
+    if (opt->force_variant > 0) {
+        const int v = std::min(opt->force_variant - 1, swf::NVAR - 1);
+        for (auto* gl : {&P.batched, &P.single})
+            for (auto& g : *gl) g.vr = g.vy = g.vz = v;
+    } else if (opt->tune) {
         int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
         if (rr) return fail(rr);
     }

@@ -1,0 +1,146 @@
+"""GPU parity at the workloads' full grid sizes, for every tile variant.
+
+* 2D grids of every benchmark length (256 ... 1024): one RK4 step from a
+  random state, element by element against the oracle's step, for each tile
+  variant forced in turn (every kernel the autotuner can pick) and both
+  precisions.
+* 3D: the lengths 256 and 320 on each axis in turn (the other axes short), so
+  the row pass and both column passes of those lengths are checked against
+  the oracle.
+* The benchmark launch configurations themselves (64 x 512^2, 8 x 256^3,
+  320^3) are too large for the oracle; there a pure-gauge field is stepped
+  through the same kernels and tiles and the scattered wave is compared at
+  sampled sites with its closed form (exp(-i Lambda) - 1) psi_back, which
+  holds at any grid size.
+FP64 to 1e-12 (one step) or 1e-5 (closed form, limited by the RK4 and
+spectral discretisation); mixed precision to 2e-6 (one step) or 3e-4
+(closed form).
+"""
+import numpy as np
+import pytest
+
+import swf_workloads as W
+from oracle.swf import SWFSolve
+
+pytestmark = pytest.mark.gpu
+
+_REF = {}
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2512_16889_amd import swf
+    return swf
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def reference_step(key, prob, k0):
+    """Random states and the oracle's one-step results, cached per problem."""
+    if key not in _REF:
+        states, refs = [], []
+        for i, sv in enumerate(prob.solves):
+            g = prob.grids[sv.grid]
+            psi = W.random_state((4,) + tuple(g.n[:g.dim]), seed=17 + i, scale=0.05)
+            states.append(psi)
+            refs.append(SWFSolve(prob, i).step(k0, psi))
+        _REF[key] = (states, refs)
+    return _REF[key]
+
+
+def one_step_case(S, key, prob, prec, variant):
+    k0 = prob.window.steps // 2
+    states, refs = reference_step(key, prob, k0)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    with S.Context(prob, precision=prec, variant=variant) as ctx:
+        for i, psi in enumerate(states):
+            ctx.set_psi(i, psi, k0)
+        ctx.step(1)
+        ctx.sync()
+        for i in range(len(states)):
+            err = relerr(ctx.get_psi(i), refs[i])
+            assert err < tol, (prec, variant, i, err)
+
+
+@pytest.mark.parametrize("n", [256, 384, 512, 768, 1024])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_2d_full_length_one_step(S, n, variant, prec):
+    prob = W.config_2d(n=n, n_solves=1, seed=n)
+    one_step_case(S, ("2d", n), prob, prec, variant)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [256, 320])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_3d_full_length_each_axis(S, axis, n, variant, prec):
+    shape = [16, 16, 16]
+    shape[axis] = n
+    L = [12.0, 12.0, 12.0]
+    L[axis] = 60.0 * n / 256
+    F = [W.Term(3, 0.8, W.sech2(8.0), [W.gauss(4.0), W.gauss(4.0), W.gauss(4.0)]),
+         W.Term(1, 0.3, W.gauss(6.0), [W.gauss(3.0), W.sech2(3.0), W.gauss(3.5)])]
+    prob = W.Problem("3d_axis", [W.Grid(3, shape, L)], [F], [W.Solve(0, 1, [0.2, -0.1, 0.5])],
+                     W.Window(-50.0, 50.0, 0.025))
+    one_step_case(S, ("3d", axis, n), prob, prec, variant)
+
+
+def pure_gauge_check(S, prob, lam0, tau, w, prec, steps, nsample=2048, variant=None):
+    """Step a pure-gauge problem and compare sampled sites with the closed form."""
+    from oracle import dirac
+    rng = np.random.default_rng(5)
+    tol = 1e-5 if prec == "fp64" else 3e-4
+    with S.Context(prob, precision=prec, tune=variant is None, variant=variant) as ctx:
+        ctx.step(steps)
+        ctx.sync()
+        t = prob.window.t_out - steps * prob.window.dt
+        for i, sv in enumerate(prob.solves):
+            g = prob.grids[sv.grid]
+            psi = ctx.get_psi(i)
+            n = g.n[:g.dim]
+            idx = [rng.integers(0, n[j], nsample) for j in range(g.dim)]
+            x = [-g.L[j] / 2 + idx[j] * g.L[j] / n[j] for j in range(g.dim)]
+            lam = lam0 * np.exp(-t ** 2 / tau ** 2 - sum(xj ** 2 for xj in x) / w ** 2)
+            wsp, E, K = dirac.background_spinor(sv.kind, sv.spin, sv.p)
+            back = wsp[:, None] * np.exp(-1j * E * t + 1j * sum(K[j] * x[j] for j in range(g.dim)))[None]
+            ref = (np.exp(-1j * lam) - 1.0)[None] * back
+            got = psi[(slice(None),) + tuple(idx)]
+            assert np.abs(ref).max() > 0.1
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+            assert err < tol, (prec, i, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_launch_config_2d_512_x64_pure_gauge(S, prec):
+    lam0, tau, w = 0.8, 4.0, 10.0
+    prob = W.config_2d(n_solves=64, t_half=60.0)
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 2)]
+    prob.window = W.Window(0.0, 24.0, 0.02)            # Lambda(t_out) ~ 1e-16; ends at the pulse maximum
+    pure_gauge_check(S, prob, lam0, tau, w, prec, prob.window.steps)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_launch_config_3d_256_x8_pure_gauge(S, prec):
+    lam0, tau, w = 0.8, 2.0, 8.0
+    prob = W.config_3d()
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 3)]
+    prob.window = W.Window(0.0, 12.0, 0.025)
+    pure_gauge_check(S, prob, lam0, tau, w, prec, prob.window.steps)
+
+
+def test_launch_config_3d_320_pure_gauge(S):
+    lam0, tau, w = 0.8, 2.0, 8.0
+    prob = W.config_bw_3d(n_p=1)
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 3)]
+    prob.vertices = []
+    prob.window = W.Window(0.0, 12.0, 0.025)
+    pure_gauge_check(S, prob, lam0, tau, w, "mixed", prob.window.steps)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_1d_1024_one_step(S, variant):
+    prob = W.config_1d()
+    one_step_case(S, ("1d",), prob, "fp64", variant)
