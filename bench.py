@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -54,6 +55,34 @@ def workload(name, time_steps=None):
     else:
         raise SystemExit(f"unknown workload {name}")
     return prob, desc
+
+
+def chosen_row_variant(report):
+    """The row-pass tile variant the autotuner kept: the fastest one it timed."""
+    times = {int(m.group(1)): float(m.group(2)) for m in re.finditer(r"row v(\d+) ([0-9.eE+-]+) ms", report)}
+    return min(times, key=times.get) if times else None
+
+
+def stored_traffic(precision, n, variant):
+    """HBM bytes per launch of the row stage pass (the mean over its four RK4
+    stages) from the committed counter summary, or None when the kernel
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if variant is None or not os.path.exists(path):
+        return None
+    from paper_2512_16889_amd.build import source_hash
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != source_hash():
+        return None
+    real = "double" if precision == "fp64" else "float"
+    per_stage = []
+    for stage in range(4):
+        k = t["kernels"].get(f"void swf::row_kernel<{real}, {n}, {variant}, 1, {stage}>(swf::PassArgs)")
+        if k is None:
+            return None
+        per_stage.append(k["fetch_bytes"] + k["write_bytes"])
+    return sum(per_stage) / 4
 
 
 def run_job(ctx, prob):
@@ -138,6 +167,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=300)
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 per-instance leg")
     ap.add_argument("--chunk", type=int, default=0, help="solves per launch group (0 = all)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile variants")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -206,9 +236,10 @@ def main():
               f"P/(psi|psi) in [{min(ratio):.2e}, {max(ratio):.2e}]", file=sys.stderr, flush=True)
         paths["fp64_batched"]["P_range"] = [min(P64), max(P64)]
         paths["fp64_batched"]["P_over_norm_range"] = [min(ratio), max(ratio)]
-        plain = partial_rate(S, torch, prob, "fp64", min(args.plain_steps, steps), batched=False)
-        paths["fp64_plain_per_instance"] = {"value": plain, "steps_timed": min(args.plain_steps, steps)}
-        print(f"[bench] fp64 plain per-instance: {plain:.4e} site-updates/s", file=sys.stderr, flush=True)
+        if not args.no_plain:
+            plain = partial_rate(S, torch, prob, "fp64", min(args.plain_steps, steps), batched=False)
+            paths["fp64_plain_per_instance"] = {"value": plain, "steps_timed": min(args.plain_steps, steps)}
+            print(f"[bench] fp64 plain per-instance: {plain:.4e} site-updates/s", file=sys.stderr, flush=True)
         if not ok:
             headline = "fp64_batched"
     H = paths[headline]
@@ -232,6 +263,10 @@ def main():
         "kernels": H["kernels"],
         "paths": paths,
     }
+    if H["roofline"]["kernel"].startswith("row pass"):
+        H["roofline"]["traffic"] = stored_traffic("fp64" if headline.startswith("fp64") else "mixed",
+                                                  prob.grids[0].n[0],
+                                                  chosen_row_variant(H.get("autotune") or ""))
     if "fp64_plain_per_instance" in paths:
         out["speedup_vs_fp64_plain"] = H["value"] / paths["fp64_plain_per_instance"]["value"]
     if not args.no_cpu:

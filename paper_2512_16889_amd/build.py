@@ -24,6 +24,19 @@ FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(HERE, "..", "include"), "-I", CSRC]
 
 
+def source_hash() -> str:
+    """sha256 over the HIP/C++ sources (sorted by name): identifies the kernels
+    a stored profile was taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
 def _jobs():
     units = [("swf_api.cpp", [], "swf_api.o"), ("swf_table.cpp", [], "swf_table.o"),
              ("swf_reduce.hip", [], "swf_reduce.o")]

@@ -626,7 +626,7 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     a.ph2 = ph2;
     a.h0row = ctx->P.grids[g.grid].dim == 1 ? 1 : 0;
     double trav = 2;
-    if (mode == swf::ROW_STAGE) trav = (stage == 0 || stage == 3) ? 5 : 7;
+    if (mode == swf::ROW_STAGE) trav = stage == 0 ? 4 : (stage == 1 ? 6 : 5);
     else if (mode == swf::ROW_RHS) trav = 3;
     const double bytes = trav * 4.0 * ctx->P.csize * group_sites(ctx, g);
     if (mode == swf::ROW_STAGE) {

@@ -292,42 +292,49 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 return;
             } else {
                 const R h = (R)(-a.dt);
-                const R h2 = (R)(-0.5 * a.dt), h3 = (R)(-a.dt / 3.0), h6 = (R)(-a.dt / 6.0);
+                const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0);
+                // Classical RK4 with the accumulator written once: with the stage
+                // inputs y_2 = y + h/2 k1, y_3 = y + h/2 k2, y_4 = y + h k3,
+                //   y_{n+1} = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
+                //           = (y_2 + 2 y_3 - y)/3 + y_4/3 + h/6 k4,
+                // so stage 1 stores acc = (y_2 + 2 y_3 - y)/3 and stage 3 finishes.
                 if constexpr (STAGE == 0) {
-                    // y_1 = y: acc = y + h/6 k1, y_2 = y + h/2 k1
-                    C acc[4][E];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int m = 0; m < E; ++m) {
-                            acc[q][m] = cadd(yi[q][m], cscale(v[q][m], h6));
-                            v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));
-                        }
-                    store(BUF_ACC, acc);
+                        for (int m = 0; m < E; ++m) v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));   // y_2
                     store(BUF_YS, v);
-                } else if constexpr (STAGE == 1 || STAGE == 2) {
-                    // acc += h/3 k, y_{i+1} = y + c h k
-                    const R hc = STAGE == 1 ? h2 : h;
+                } else if constexpr (STAGE == 1) {
+                    const R third = (R)(1.0 / 3.0);
                     C y0[4][E], acc[4][E];
                     load(BUF_Y, y0);
-                    load(BUF_ACC, acc);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
                         for (int m = 0; m < E; ++m) {
-                            acc[q][m] = cadd(acc[q][m], cscale(v[q][m], h3));
-                            v[q][m] = cadd(y0[q][m], cscale(v[q][m], hc));
+                            const C y3 = cadd(y0[q][m], cscale(v[q][m], h2));
+                            acc[q][m] = cscale(csub(cadd(yi[q][m], cscale(y3, (R)2)), y0[q][m]), third);
+                            v[q][m] = y3;
                         }
                     store(BUF_ACC, acc);
                     store(BUF_YS, v);
+                } else if constexpr (STAGE == 2) {
+                    C y0[4][E];
+                    load(BUF_Y, y0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int m = 0; m < E; ++m) v[q][m] = cadd(y0[q][m], cscale(v[q][m], h));   // y_4
+                    store(BUF_YS, v);
                 } else {
-                    // y_{n+1} = acc + h/6 k4, then the boundary mask
+                    const R third = (R)(1.0 / 3.0);
                     C acc[4][E];
                     load(BUF_ACC, acc);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int m = 0; m < E; ++m) v[q][m] = cadd(acc[q][m], cscale(v[q][m], h6));
+                        for (int m = 0; m < E; ++m)
+                            v[q][m] = cadd(cadd(acc[q][m], cscale(yi[q][m], third)), cscale(v[q][m], h6));
                     const long long mask = S->mask;
                     if (mask >= 0) {
                         const R myz = rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
