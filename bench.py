@@ -113,7 +113,7 @@ def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profi
     ctx.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stats = {k: ctx.kernel_stats(k) for k in range(5)} if profile else {}
+    stats = {k: ctx.kernel_stats(k) for k in range(6)} if profile else {}
     norms = [ctx.diagnostics(i)[0] for i in range(len(prob.solves))]
     ctx.close()
     return wall, results, stats, report, norms
@@ -121,7 +121,7 @@ def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profi
 
 def partial_rate(S, torch, prob, precision, nsteps, batched, tune=False):
     """Site-updates/s of a shorter run (work is linear in the step count)."""
-    ctx = S.Context(prob, precision=precision, batched=batched, tune=tune)
+    ctx = S.Context(prob, precision=precision, batched=batched, tune=tune, persistent=batched)
     ctx.step(min(20, nsteps))
     ctx.sync()
     ctx.reset()
@@ -199,7 +199,8 @@ def main():
           file=sys.stderr, flush=True)
 
     names = {0: "row pass (x FFTs + RK4 stage epilogue)", 1: "column pass y (stepping)",
-             2: "column pass z (stepping)", 3: "BW vertex reduction", 4: "t_in transforms"}
+             2: "column pass z (stepping)", 3: "BW vertex reduction", 4: "t_in transforms",
+             5: "1D whole-loop kernel (all steps on chip)"}
 
     def summarize(wall, stats):
         dom = max((k for k in stats if k != 4), key=lambda k: stats[k][1])

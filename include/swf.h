@@ -112,6 +112,14 @@ typedef struct {
                                next, so a chunk's arrays can stay in the on-die cache  */
     int force_variant;      /* > 0: use tile variant force_variant - 1 (0..3) for every pass
                                (testing); 0: the autotuned or the default variant       */
+    int persistent;         /* 1: when every grid is one-dimensional with a power-of-two
+                               length 64..1024, the field's profile tables fit in LDS
+                               next to the state (FP64, 1024 points: up to 4 terms) and
+                               there are no BW vertices, each swf_step call runs all its
+                               time steps in one kernel per launch group (at most 1024
+                               steps per launch), one workgroup per solve, with the state
+                               held on chip; otherwise, and with 0, one launch per pass
+                               and RK4 stage                                            */
 } swf_options;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */
@@ -197,8 +205,9 @@ swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in,
 
 /* Pass timing collected when options.profile = 1.  kind: 0 row pass (x axis,
  * with the stage epilogue), 1 column pass (y axis), 2 column pass (z axis),
- * 3 BW vertex reduction, 4 other.  Returns launches, summed device milliseconds
- * and the algorithmic HBM bytes those launches move (state reads + writes). */
+ * 3 BW vertex reduction, 4 other, 5 one-dimensional whole-loop kernel
+ * (options.persistent).  Returns launches, summed device milliseconds and the
+ * algorithmic HBM bytes those launches move (state reads + writes). */
 swf_status swf_kernel_stats(swf_ctx* ctx, int kind, long long* launches, double* ms, double* bytes);
 swf_status swf_reset_stats(swf_ctx* ctx);
 

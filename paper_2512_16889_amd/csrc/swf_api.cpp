@@ -36,6 +36,8 @@ thread_local std::string g_init_error;
 
 constexpr int RED_BLOCKS = 512;          // blocks of every reduction launch (fixed: deterministic sums)
 constexpr int BW_BLOCKS = 256;           // blocks per vertex of the BW stage reduction
+constexpr size_t LINE_STATIC_LDS = 1024;  // bound on the line kernel's static LDS
+constexpr int NKIND = 6;                 // kernel-stats kinds (swf_kernel_stats)
 constexpr int PROF_POOL = 2048;          // event pairs kept in flight when profiling
 
 const double PI = 3.14159265358979323846;
@@ -488,6 +490,7 @@ struct swf_ctx {
     bool own_arena = false;
     int step = 0;
     bool t_valid = true;
+    size_t lds_max = 65536;       // dynamic LDS one workgroup may use on this device
     std::vector<char> kvalid;
     std::vector<int> bw_done;
     std::vector<cd> bw_cache;     // 3 terms finite + 3 past per vertex
@@ -499,9 +502,9 @@ struct swf_ctx {
     // profiling
     std::vector<hipEvent_t> ev_free;
     std::vector<PendingEv> pending;
-    long long st_launch[5] = {0, 0, 0, 0, 0};
-    double st_ms[5] = {0, 0, 0, 0, 0};
-    double st_bytes[5] = {0, 0, 0, 0, 0};
+    long long st_launch[NKIND] = {};
+    double st_ms[NKIND] = {};
+    double st_bytes[NKIND] = {};
 
     SolveDev* d_solves() { return (SolveDev*)(arena + P.off_solves); }
     TermDev* d_terms() { return (TermDev*)(arena + P.off_terms); }
@@ -592,11 +595,11 @@ static double group_sites(swf_ctx* ctx, const Group& g) {
 
 // Launch one pass kernel over n items starting at item offset `it`.
 static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threads, size_t lds, swf::PassArgs a,
-                  int kind, double bytes, int tiles = 1) {
+                  int kind, double bytes) {
     if (nitems <= 0) return SWF_OK;
     a.items = ctx->d_items() + it;
     a.nitems = nitems;
-    const int blocks = (nitems + tiles - 1) / tiles;
+    const int blocks = nitems;
     void* args[] = {&a};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = ctx->opt.profile && !ctx->gexec;
@@ -645,7 +648,7 @@ static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, 
     const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
     const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
     return launch(ctx, cv.fn[axis - 1][mode], n, it, cv.threads, cv.lds, a, kind,
-                  2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g), cv.tiles);
+                  2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g));
 }
 
 // k-space kinetic pass of a group (between the forward x pass and the row epilogue).
@@ -746,6 +749,60 @@ static int enqueue_step(swf_ctx* ctx) {
     int r = bw_accum(ctx);
     if (r) return r;
     HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
+    return SWF_OK;
+}
+
+// One-dimensional whole-loop path: every group is a 1D grid with a line
+// kernel and no vertex couples two solves.
+static size_t line_lds(const swf_ctx* ctx, const Group& g, int nterm_max, int wide) {
+    return g.k[0]->line_lds[wide] + (size_t)nterm_max * ctx->P.grids[g.grid].n[0] * ctx->P.rsize;
+}
+
+static int max_terms(const swf_ctx* ctx, const Group& g) {
+    int m = 0;
+    for (int i : g.solves) m = std::max(m, ctx->P.hs[i].nterm);
+    return m;
+}
+
+// The line kernel build a group runs: 1 wide exchange rounds, 0 narrow, -1
+// none fits the LDS of one workgroup.
+static int line_build(const swf_ctx* ctx, const Group& g) {
+    if (ctx->P.grids[g.grid].dim != 1 || !g.k[0]->line[0]) return -1;
+    const int nt = max_terms(ctx, g);
+    for (int w = 1; w >= 0; --w)
+        if (line_lds(ctx, g, nt, w) + LINE_STATIC_LDS <= ctx->lds_max) return w;
+    return -1;
+}
+
+// One-dimensional whole-loop path: every group is a 1D grid with a line
+// kernel whose LDS (with the group's field terms) fits, and no vertex couples
+// two solves.
+static bool line_path(swf_ctx* ctx) {
+    if (!ctx->opt.persistent || !ctx->P.hv.empty()) return false;
+    for (const auto& g : groups(ctx))
+        if (line_build(ctx, g) < 0) return false;
+    return true;
+}
+
+// n RK4 steps of every solve: launches of at most LINE_STEPS steps each, then
+// the device step counter is advanced by the same count.
+constexpr int LINE_STEPS = 1024;
+static int line_steps(swf_ctx* ctx, int n) {
+    for (int done = 0; done < n;) {
+        const int c = std::min(LINE_STEPS, n - done);
+        for (const auto& g : groups(ctx)) {
+            swf::PassArgs a = pass_args(ctx);
+            a.nsteps = c;
+            const double bytes = 2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g);
+            const int w = line_build(ctx, g);
+            int r = launch(ctx, g.k[0]->line[w], g.n_row[0], g.it_row[0], g.k[0]->line_threads,
+                           line_lds(ctx, g, max_terms(ctx, g), w), a, 5, bytes);
+            if (r) return r;
+        }
+        HIPCHK(swf::launch_advance(ctx->d_step(), c, ctx->st));
+        done += c;
+    }
+    ctx->t_valid = false;   // the FFT buffer no longer holds the transform of Y
     return SWF_OK;
 }
 
@@ -1181,6 +1238,12 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     INITCHK(hipMemsetAsync(ctx->d_step(), 0, 256, ctx->st));
     INITCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, P.hv.size()), ctx->st));
     INITCHK(hipStreamSynchronize(ctx->st));
+    {
+        int dev = 0, lds = 0;
+        INITCHK(hipGetDevice(&dev));
+        INITCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        ctx->lds_max = (size_t)lds;
+    }
     // allow the dynamic LDS every pass kernel of these sizes asks for
     for (const auto* gl : {&P.batched, &P.single})
         for (const auto& g : *gl)
@@ -1189,6 +1252,11 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 if (!k) continue;
                 for (int m = 0; m < 5; ++m)
                     INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
+                if (k->line[0] && ax == 0)
+                    for (int w = 0; w < 2; ++w)
+                        INITCHK(hipFuncSetAttribute(k->line[w], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)std::min(ctx->lds_max - LINE_STATIC_LDS,
+                                                                  line_lds(ctx, g, swf::MAX_TERMS, w))));
                 for (int v = 0; v < swf::NVAR; ++v) {
                     for (int st = 0; st < 4; ++st)
                         INITCHK(hipFuncSetAttribute(k->row[v].stage[st], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
@@ -1204,7 +1272,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         const int v = std::min(opt->force_variant - 1, swf::NVAR - 1);
         for (auto* gl : {&P.batched, &P.single})
             for (auto& g : *gl) g.vr = g.vy = g.vz = v;
-    } else if (opt->tune) {
+    } else if (opt->tune && !line_path(ctx)) {
         int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
         if (rr) return fail(rr);
     }
@@ -1229,14 +1297,19 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
     }
     int r = enter(ctx);
     if (r) return (swf_status)r;
-    r = refresh_T(ctx);
-    if (r) return (swf_status)r;
-    for (int i = 0; i < n_steps; ++i) {
-        if (ctx->gexec) {
-            HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
-        } else {
-            r = enqueue_step(ctx);
-            if (r) return (swf_status)r;
+    if (line_path(ctx)) {
+        r = line_steps(ctx, n_steps);
+        if (r) return (swf_status)r;
+    } else {
+        r = refresh_T(ctx);
+        if (r) return (swf_status)r;
+        for (int i = 0; i < n_steps; ++i) {
+            if (ctx->gexec) {
+                HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
+            } else {
+                r = enqueue_step(ctx);
+                if (r) return (swf_status)r;
+            }
         }
     }
     if (n_steps > 0) {
@@ -1488,7 +1561,7 @@ swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in,
 }
 
 swf_status swf_kernel_stats(swf_ctx* ctx, int kind, long long* launches, double* ms, double* bytes) {
-    if (!ctx || kind < 0 || kind > 4) return SWF_E_ARG;
+    if (!ctx || kind < 0 || kind >= NKIND) return SWF_E_ARG;
     int r = drain_profile(ctx);
     if (r) return (swf_status)r;
     if (launches) *launches = ctx->st_launch[kind];
@@ -1501,7 +1574,7 @@ swf_status swf_reset_stats(swf_ctx* ctx) {
     if (!ctx) return SWF_E_ARG;
     int r = drain_profile(ctx);
     if (r) return (swf_status)r;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < NKIND; ++k) {
         ctx->st_launch[k] = 0;
         ctx->st_ms[k] = 0;
         ctx->st_bytes[k] = 0;

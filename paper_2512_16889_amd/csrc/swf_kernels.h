@@ -35,6 +35,7 @@ struct PassArgs {
     double t_explicit;     // time of ROW_RHS
     long long ph2;         // ROW_FWDPH: complex offset of exp(i k_j x_j) tables
     int nitems;            // work items of this launch
+    int nsteps;            // line_kernel: RK4 steps per launch
 };
 
 // ------------------------------------------------------------------ tile variants
@@ -93,7 +94,6 @@ template <class R, int N, int V> struct ColVar {
     static constexpr int CG = V == 3 ? imin(2, cg_fit(PER_COMP)) : 1;
     static constexpr size_t BYTES = CG * PER_COMP;
     static constexpr bool SEQ = false;
-    static constexpr int TILES = 1;
     static_assert(plan_ok<N, T, PL>(), "column variant violates the FFT plan constraints");
 };
 
@@ -364,105 +364,267 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
     constexpr int W = VC::W;
     constexpr int CG = VC::CG;
     constexpr int E = N / T;
-    constexpr int TPB = VC::TILES;
     using Lay = ColLay<N, W>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
+    __shared__ C tw[N];
 
     const int tid = threadIdx.x;
     const int xl = tid % W;
     const int t = tid / W;
 
-    // One tile = W adjacent columns of one solve, one fixed other-axis index.
-    struct Tile {
-        const SolveDev* S;
-        C* buf;
-        long long base, stride, ns;
-        int x, other, n0, n1;
-        bool act;
-    };
-    auto decode = [&](int item) {
-        Tile c;
-        const int2 it = a.items[item];
-        c.S = a.solves + it.x;
-        c.n0 = c.S->n[0];
-        c.n1 = c.S->n[1];
-        const int ntx = (c.n0 + W - 1) / W;
-        c.other = it.y / ntx;
-        c.x = (it.y % ntx) * W + xl;
-        c.act = c.x < c.n0;
-        c.stride = AXIS == 1 ? (long long)c.n0 : (long long)c.n0 * c.n1;
-        const long long obase = AXIS == 1 ? (long long)c.other * c.n0 * c.n1 : (long long)c.other * c.n0;
-        c.base = obase + (c.act ? c.x : 0);
-        c.ns = c.S->nsites;
-        c.buf = reinterpret_cast<C*>(c.S->buf[a.dst]);
-        return c;
-    };
-    auto load = [&](const Tile& c, C (&w)[4][E]) {
+    // One tile = W adjacent columns of one solve at one fixed other-axis index.
+    const int2 it = a.items[blockIdx.x];
+    const SolveDev* __restrict__ S = a.solves + it.x;
+    const int n0 = S->n[0], n1 = S->n[1];
+    const int ntx = (n0 + W - 1) / W;
+    const int other = it.y / ntx;
+    const int x = (it.y % ntx) * W + xl;
+    const bool act = x < n0;
+    const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
+    const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
+    const long long base = obase + (act ? x : 0) + (long long)t * stride;
+    const long long ns = S->nsites;
+
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[AXIS] + i);
+
+    C v[4][E];
+    {
+        gptr<const nv2<R>> p = cview<R>(S->buf[a.dst]) + base;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) w[q][m] = c.buf[q * c.ns + c.base + (long long)(t + T * m) * c.stride];
-    };
-
-    const int first = blockIdx.x * TPB;
-    Tile cur = decode(first);
-    __shared__ C tw[N];
-    {
-        const C* __restrict__ twg = reinterpret_cast<const C*>(a.ctab) + cur.S->tw[AXIS];
-        for (int i = tid; i < N; i += VC::THREADS) tw[i] = twg[i];
+            for (int m = 0; m < E; ++m) v[q][m] = gload<C>(p, q * ns + (long long)(T * m) * stride);
     }
-    C v[4][E];
-    load(cur, v);
+    if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
+    if constexpr (MODE == COL_H0) {
+        const R s = (R)S->inv_n;
+        const R Kx = (R)(S->dk[0] * kindex(act ? x : 0, n0));
 #pragma unroll
-    for (int k = 0; k < TPB; ++k) {
-        // software pipeline: the next tile's loads are in flight while this
-        // tile is transformed
-        const bool has_next = (k + 1 < TPB) && (first + k + 1 < a.nitems);
-        Tile nxt;
-        C vn[4][E];
-        if (has_next) {
-            nxt = decode(first + k + 1);
-            load(nxt, vn);
+        for (int m = 0; m < E; ++m) {
+            const int idx = t + T * m;
+            R Ky, Kz;
+            if constexpr (AXIS == 1) {
+                Ky = (R)(S->dk[1] * kindex(idx, N));
+                Kz = (R)S->kap[2];
+            } else {
+                Ky = (R)(S->dk[1] * kindex(other, n1));
+                Kz = (R)(S->dk[2] * kindex(idx, N));
+            }
+            apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
         }
-        if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
-        if constexpr (MODE == COL_H0) {
-            const SolveDev* S = cur.S;
-            const R s = (R)S->inv_n;
-            const R Kx = (R)(S->dk[0] * kindex(cur.act ? cur.x : 0, cur.n0));
+    }
+    if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
+    if (act) {
+        gptr<nv2<R>> p = wview<R>(S->buf[a.dst]) + base;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore<C>(p, q * ns + (long long)(T * m) * stride, v[q][m]);
+    }
+}
+
+// ------------------------------------------------------------------ 1D whole-loop kernel
+// A (1+1)D solve is one line of at most 1024 points: its whole state fits on
+// one compute unit.  line_kernel runs a.nsteps complete RK4 steps of one solve
+// per workgroup without leaving the chip: the state y and the stage input stay
+// in registers, the running RK4 sum in thread-private LDS slots, and each stage
+// transforms the line forward, multiplies by -i H0(k)/N and transforms back
+// through LDS.  Only the final state is written to the Y array.  The update is
+// the classical y_{n+1} = y + h/6 (k1 + 2 k2 + 2 k3 + k4) with h = -dt,
+// accumulated stage by stage.  Field profiles, background phases, the absorber
+// mask and the twiddles are staged in LDS once per launch; the per-stage time
+// factors are evaluated in double by a few lanes and broadcast through LDS.
+// WIDE: the exchange rounds move CGW components at once (fewer barriers, more
+// LDS); otherwise half as many.  The host takes the wide build where its LDS,
+// with the field's profile tables, fits.
+template <class R, int N, bool WIDE> struct LineVar {
+    using PL = Plan4<N>;
+    static constexpr int T = PL::T;
+    static constexpr int E = N / T;
+    using Lay = RowLay<N, 1>;
+    static constexpr int CGW = sizeof(R) == 8 ? 2 : 4;
+    static constexpr int CG = WIDE ? CGW : CGW / 2;
+    static constexpr size_t XCH = CG * (size_t)Lay::STRIDE * sizeof(cpx<R>);
+    // dynamic LDS without the field profiles: exchange, twiddles, phases,
+    // RK4 sum, mask (the host adds nterm * N reals)
+    static constexpr size_t BASE_BYTES = XCH + 2 * N * sizeof(cpx<R>) + 4 * N * sizeof(cpx<R>) + N * sizeof(R);
+    static_assert(PL::NR >= 2, "the stage broadcast relies on the barriers of the exchanges");
+    static_assert(plan_ok<N, T, PL>(), "line plan violates the FFT plan constraints");
+};
+
+// A zero the compiler cannot see through.  Offsetting the lane index with it
+// once per transform keeps the (loop-invariant) exchange addresses from being
+// hoisted out of the time loop into registers.
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+template <class R, int N, bool WIDE>
+__global__ void __launch_bounds__((LineVar<R, N, WIDE>::T)) line_kernel(PassArgs a) {
+    using C = cpx<R>;
+    using VC = LineVar<R, N, WIDE>;
+    constexpr int T = VC::T;
+    constexpr int E = VC::E;
+    constexpr int CG = VC::CG;
+    using Lay = typename VC::Lay;
+    using PL = typename VC::PL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* xch = reinterpret_cast<C*>(smem_raw);
+    C* tw = reinterpret_cast<C*>(smem_raw + VC::XCH);
+    C* phx = tw + N;                               // exp(i K.x) on the line (trivial axes folded in)
+    C* accl = phx + N;                             // RK4 sum, [q][m][lane]
+    R* msk = reinterpret_cast<R*>(accl + 4 * N);   // absorber mask (1 if off)
+    R* fx = msk + N;                               // spatial profile of each field term
+    __shared__ R sh_coef[2][MAX_TERMS];            // amp * f_t(t) per term, double-buffered by stage
+    __shared__ C sh_wc[2][4];                      // background spinor * exp(-i E t)
+    __shared__ int sh_mu[MAX_TERMS];
+
+    const int t = threadIdx.x;
+    const SolveDev* __restrict__ S = a.solves + a.items[blockIdx.x].x;
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
+    const int nterm = S->nterm;
+    {
+        // trivial axes (index 0 of each): constant factors of the tables
+        const C phyz = cmul(gload<C>(ctab, S->ph + N), gload<C>(ctab, S->ph + N + 1));
+        const long long mk = S->mask;
+        const R myz = mk >= 0 ? rtab[mk + N] * rtab[mk + N + 1] : (R)1;
+        for (int i = t; i < N; i += T) {
+            tw[i] = gload<C>(ctab, S->tw[0] + i);
+            phx[i] = cmul(gload<C>(ctab, S->ph + i), phyz);
+            msk[i] = mk >= 0 ? rtab[mk + i] * myz : (R)1;
+        }
+        for (int j = 0; j < nterm; ++j) {
+            const long long tb = a.terms[S->term0 + j].tab;
+            const R fyz = rtab[tb + N] * rtab[tb + N + 1];
+            for (int i = t; i < N; i += T) fx[j * N + i] = rtab[tb + i] * fyz;
+        }
+        if (t < nterm) sh_mu[t] = a.terms[S->term0 + t].mu;
+    }
+    C y[4][E];
+    {
+        gptr<const nv2<R>> p = cview<R>(S->buf[BUF_Y]) + t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) y[q][m] = gload<C>(p, q * (long long)N + T * m);
+    }
+    __syncthreads();
+
+    const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], inv_n = (R)S->inv_n;
+    const double dk = S->dk[0];
+    const double dt = a.dt;
+    const R h = (R)(-dt), h2 = (R)(-0.5 * dt), h3 = (R)(-dt / 3.0), h6 = (R)(-dt / 6.0);
+    const int n_first = *a.step;
+
+    // v = IFFT[-i H0 FFT(yi)]/N - i V(ts) (yi + psi_b(ts)); par selects the
+    // broadcast buffer of this stage
+    auto rhs = [&](const C (&yi)[4][E], C (&v)[4][E], double ts, int par) {
+        for (int j = t; j < nterm; j += T) {
+            const TermDev tm = a.terms[S->term0 + j];
+            sh_coef[par][j] = (R)(tm.amp * profile_t(tm.ft_type, tm.c, tm.w, tm.k, tm.phi, ts));
+        }
+        if (t >= T - 4) {
+            const int q = t - (T - 4);
+            double sn, cs;
+            sincos(-S->E * ts, &sn, &cs);
+            const double wr = S->w[2 * q], wi = S->w[2 * q + 1];
+            sh_wc[par][q] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[q][m] = yi[q][m];
+        // the exchanges' barriers also publish sh_coef / sh_wc
+        const int tf = t + opaque_zero();
+        fft_line<C, N, T, -1, 4, CG, Lay, PL>(v, xch, tf, 0, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], (R)(dk * kindex(tf + T * m, N)), Ky, Kz, inv_n);
+        const int ti = t + opaque_zero();
+        fft_line<C, N, T, +1, 4, CG, Lay, PL>(v, xch, ti, 0, tw);
+        const C wc[4] = {sh_wc[par][0], sh_wc[par][1], sh_wc[par][2], sh_wc[par][3]};
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = ti + T * m;
+            R A[4] = {(R)0, (R)0, (R)0, (R)0};
+            for (int j = 0; j < nterm; ++j) {
+                const R f = sh_coef[par][j] * fx[j * N + i];
+                const int mu = sh_mu[j];
+                A[0] += mu == 0 ? f : (R)0;
+                A[1] += mu == 1 ? f : (R)0;
+                A[2] += mu == 2 ? f : (R)0;
+                A[3] += mu == 3 ? f : (R)0;
+            }
+            const C ph = phx[i];
+            C sv[4], vs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sv[q] = cadd(yi[q][m], cmul(wc[q], ph));
+            apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));
+        }
+    };
+    // this lane's RK4 sum slot of component q, point m
+    auto acc = [&](int q, int m) -> C& { return accl[(q * E + m) * T + t]; };
+
+#pragma unroll 1
+    for (int n = 0; n < a.nsteps; ++n) {
+        const double tn = a.t_out - (double)(n_first + n) * dt;
+        C yi[4][E], k[4][E];
+        // stage 1 at t_n
+        rhs(y, k, tn, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                const int idx = t + T * m;
-                R Ky, Kz;
-                if constexpr (AXIS == 1) {
-                    Ky = (R)(S->dk[1] * kindex(idx, N));
-                    Kz = (R)S->kap[2];
-                } else {
-                    Ky = (R)(S->dk[1] * kindex(cur.other, cur.n1));
-                    Kz = (R)(S->dk[2] * kindex(idx, N));
-                }
-                apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+                acc(q, m) = cadd(y[q][m], cscale(k[q][m], h6));
+                yi[q][m] = cadd(y[q][m], cscale(k[q][m], h2));
             }
-        }
-        if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
-        if (cur.act) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int m = 0; m < E; ++m) cur.buf[q * cur.ns + cur.base + (long long)(t + T * m) * cur.stride] = v[q][m];
-        }
-        if (!has_next) break;
-        cur = nxt;
+        // stage 2 at t_n + h/2
+        rhs(yi, k, tn - 0.5 * dt, 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[q][m] = vn[q][m];
+            for (int m = 0; m < E; ++m) {
+                acc(q, m) = cadd(acc(q, m), cscale(k[q][m], h3));
+                yi[q][m] = cadd(y[q][m], cscale(k[q][m], h2));
+            }
+        // stage 3 at t_n + h/2
+        rhs(yi, k, tn - 0.5 * dt, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                acc(q, m) = cadd(acc(q, m), cscale(k[q][m], h3));
+                yi[q][m] = cadd(y[q][m], cscale(k[q][m], h));
+            }
+        // stage 4 at t_n + h, then the absorber
+        rhs(yi, k, tn - dt, 1);
+        const int o = opaque_zero();
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const R mk = msk[t + T * m + o];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) y[q][m] = cscale(cadd(acc(q, m), cscale(k[q][m], h6)), mk);
+        }
+    }
+    {
+        gptr<nv2<R>> p = wview<R>(S->buf[BUF_Y]) + t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore<C>(p, q * (long long)N + T * m, y[q][m]);
     }
 }
 
 // Kernel table of one (precision, N) instantiation.
 struct RowVariant { const void* stage[4]; int threads, rows; size_t lds; };
-struct ColVariant { const void* fn[2][3]; int threads, w, tiles; size_t lds; };
+struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
     int nvar;
     RowVariant row[NVAR];          // the RK4 stage pass, by variant
@@ -470,6 +632,10 @@ struct SizeKernels {
     int row0_threads, row0_rows;
     size_t row0_lds;
     ColVariant col[NVAR];
+    const void* line[2];           // 1D whole-loop kernel, narrow / wide exchange rounds
+                                   // (NULL where there is no 4-point plan)
+    int line_threads;
+    size_t line_lds[2];            // their dynamic LDS without the field-term profiles
 };
 
 template <class R, int N, int V>
@@ -491,7 +657,6 @@ ColVariant make_col_variant() {
     c.fn[1][COL_H0] = (const void*)col_kernel<R, N, V, COL_H0, 2>;
     c.threads = VC::THREADS;
     c.w = VC::W;
-    c.tiles = VC::TILES;
     c.lds = VC::BYTES;
     return c;
 }
@@ -523,6 +688,17 @@ SizeKernels make_size_kernels() {
     k.row0_threads = RowVar<R, N, 0>::THREADS;
     k.row0_rows = RowVar<R, N, 0>::ROWS;
     k.row0_lds = RowVar<R, N, 0>::BYTES;
+    if constexpr (has_plan4<N>()) {
+        k.line[0] = (const void*)line_kernel<R, N, false>;
+        k.line[1] = (const void*)line_kernel<R, N, true>;
+        k.line_threads = LineVar<R, N, false>::T;
+        k.line_lds[0] = LineVar<R, N, false>::BASE_BYTES;
+        k.line_lds[1] = LineVar<R, N, true>::BASE_BYTES;
+    } else {
+        k.line[0] = k.line[1] = nullptr;
+        k.line_threads = 0;
+        k.line_lds[0] = k.line_lds[1] = 0;
+    }
     return k;
 }
 

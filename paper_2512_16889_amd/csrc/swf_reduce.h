@@ -44,6 +44,7 @@ hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hi
 hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_tick(int* step, hipStream_t st);
+hipError_t launch_advance(int* step, int n, hipStream_t st);
 
 struct SizeKernels;
 // Kernel table of an FFT length for single (fp64 = 0) or double precision, NULL if unsupported.

@@ -320,8 +320,8 @@ __global__ void bw_accum_kernel(BwArgs a, int nblk) {
     *M = dadd(*M, dsc(s, f));
 }
 
-__global__ void tick_kernel(int* step) {
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(step, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__global__ void tick_kernel(int* step, int n) {
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(step, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -356,8 +356,10 @@ hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_tick(int* step, hipStream_t st) {
-    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, st, step);
+hipError_t launch_tick(int* step, hipStream_t st) { return launch_advance(step, 1, st); }
+
+hipError_t launch_advance(int* step, int n, hipStream_t st) {
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, st, step, n);
     return hipGetLastError();
 }
 

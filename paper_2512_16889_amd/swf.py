@@ -64,7 +64,7 @@ class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int), ("batched", C.c_int),
                 ("profile", C.c_int), ("tune", C.c_int), ("tune_cache", C.c_char_p), ("chunk", C.c_int),
-                ("force_variant", C.c_int)]
+                ("force_variant", C.c_int), ("persistent", C.c_int)]
 
 
 _P = C.POINTER
@@ -160,7 +160,8 @@ class Context:
 
     def __init__(self, problem, precision: str = "fp64", use_graph: bool = False, batched: bool = True,
                  profile: bool = False, device_workspace: bool = True, tune: bool = False,
-                 tune_cache: str | None = None, chunk: int = 0, variant: int | None = None):
+                 tune_cache: str | None = None, chunk: int = 0, variant: int | None = None,
+                 persistent: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("the SWF solver runs on the GPU only; no device is visible")
         self.problem = problem
@@ -174,6 +175,7 @@ class Context:
         self.opt.tune = int(tune)
         self.opt.chunk = int(chunk)
         self.opt.force_variant = 0 if variant is None else int(variant) + 1
+        self.opt.persistent = int(persistent)
         self._tune_cache = tune_cache.encode() if tune_cache else None
         self.opt.tune_cache = self._tune_cache
         self.opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)

@@ -7,6 +7,8 @@
 * 3D: the lengths 256 and 320 on each axis in turn (the other axes short), so
   the row pass and both column passes of those lengths are checked against
   the oracle.
+* The (1+1)D line of 1024 points: one step through every pass-path tile
+  variant and through the whole-loop kernel, against the oracle.
 * The benchmark launch configurations themselves (64 x 512^2, 8 x 256^3,
   320^3) are too large for the oracle; there a pure-gauge field is stepped
   through the same kernels and tiles and the scattered wave is compared at
@@ -50,11 +52,11 @@ def reference_step(key, prob, k0):
     return _REF[key]
 
 
-def one_step_case(S, key, prob, prec, variant):
+def one_step_case(S, key, prob, prec, variant, persistent=True):
     k0 = prob.window.steps // 2
     states, refs = reference_step(key, prob, k0)
     tol = 1e-12 if prec == "fp64" else 2e-6
-    with S.Context(prob, precision=prec, variant=variant) as ctx:
+    with S.Context(prob, precision=prec, variant=variant, persistent=persistent) as ctx:
         for i, psi in enumerate(states):
             ctx.set_psi(i, psi, k0)
         ctx.step(1)
@@ -142,5 +144,12 @@ def test_launch_config_3d_320_pure_gauge(S):
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_1d_1024_one_step(S, variant):
+    # the pass path's tile variants (the whole-loop kernel switched off)
     prob = W.config_1d()
-    one_step_case(S, ("1d",), prob, "fp64", variant)
+    one_step_case(S, ("1d",), prob, "fp64", variant, persistent=False)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_1d_1024_one_step_whole_loop(S, prec):
+    prob = W.config_1d()
+    one_step_case(S, ("1d",), prob, prec, None)
