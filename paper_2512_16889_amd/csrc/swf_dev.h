@@ -112,6 +112,29 @@ SWF_PLAN4(1024, 4, 4, 4, 4, 4)
 #undef SWF_PLAN4
 template <int N> constexpr bool has_plan4() { return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024; }
 
+// Plans with few points per thread for the mixed-radix lengths: a radix-6
+// (3 * 2^a) or radix-10 (5 * 2^a) first step and radix-2 steps after it, so a
+// thread holds 6 or 10 points instead of 12 or 20 (the default plans' radix-4
+// steps need a multiple of 4 and of 3 or 5 per thread).
+template <int N> struct PlanS;
+#define SWF_PLANS(N_, E_, ...)                                           \
+    template <> struct PlanS<N_> {                                       \
+        static constexpr int T = N_ / E_;                                \
+        static constexpr int R[] = {__VA_ARGS__};                        \
+        static constexpr int NR = sizeof(R) / sizeof(int);               \
+    };
+SWF_PLANS(384, 6, 6, 2, 2, 2, 2, 2, 2)
+SWF_PLANS(768, 6, 6, 2, 2, 2, 2, 2, 2, 2)
+SWF_PLANS(320, 10, 10, 2, 2, 2, 2, 2)
+#undef SWF_PLANS
+template <int N> constexpr bool has_plans() { return N == 384 || N == 768 || N == 320; }
+
+// The few-points-per-thread plan of a length (tile variants that use it).
+template <int N, bool P4 = has_plan4<N>(), bool PS = has_plans<N>()> struct SmallPlan { using type = FftPlan<N>; };
+template <int N, bool PS> struct SmallPlan<N, true, PS> { using type = Plan4<N>; };
+template <int N> struct SmallPlan<N, false, true> { using type = PlanS<N>; };
+template <int N> constexpr bool has_small_plan() { return has_plan4<N>() || has_plans<N>(); }
+
 template <class P> constexpr int plan_stride(int j) {
     int s = 1;
     for (int i = 0; i < j; ++i) s *= P::R[i];
@@ -191,6 +214,51 @@ template <int DIR, class C> struct Dft<8, DIR, C> {
         for (int q = 0; q < 4; ++q) {
             a[q] = cadd(e[q], o[q]);
             a[q + 4] = csub(e[q], o[q]);
+        }
+    }
+};
+
+// radix 6 = 2 x 3: y[k] = E[k mod 3] + w^k O[k mod 3], w = exp(DIR 2 pi i / 6),
+// E and O the 3-point transforms of the even and odd inputs (w^3 = -1)
+template <int DIR, class C> struct Dft<6, DIR, C> {
+    static __device__ __forceinline__ void run(C* a) {
+        using R = decltype(C::x);
+        const R h = (R)0.5, s = (R)(DIR * 0.86602540378443864676);   // w = h + i s, w^2 = -h + i s
+        C e[3] = {a[0], a[2], a[4]};
+        C o[3] = {a[1], a[3], a[5]};
+        Dft<3, DIR, C>::run(e);
+        Dft<3, DIR, C>::run(o);
+        const C o1 = cmul(o[1], cmake<C>(h, s));
+        const C o2 = cmul(o[2], cmake<C>(-h, s));
+        a[0] = cadd(e[0], o[0]);
+        a[3] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], o1);
+        a[4] = csub(e[1], o1);
+        a[2] = cadd(e[2], o2);
+        a[5] = csub(e[2], o2);
+    }
+};
+
+// radix 10 = 2 x 5, the same even/odd split around the 5-point transform
+template <int DIR, class C> struct Dft<10, DIR, C> {
+    static __device__ __forceinline__ void run(C* a) {
+        using R = decltype(C::x);
+        const R c1 = (R)0.80901699437494742410, s1 = (R)(DIR * 0.58778525229247312917);   // w^1 (36 degrees)
+        const R c2 = (R)0.30901699437494742410, s2 = (R)(DIR * 0.95105651629515357212);   // w^2 (72)
+        C e[5] = {a[0], a[2], a[4], a[6], a[8]};
+        C o[5] = {a[1], a[3], a[5], a[7], a[9]};
+        Dft<5, DIR, C>::run(e);
+        Dft<5, DIR, C>::run(o);
+        C ow[5];
+        ow[0] = o[0];
+        ow[1] = cmul(o[1], cmake<C>(c1, s1));
+        ow[2] = cmul(o[2], cmake<C>(c2, s2));
+        ow[3] = cmul(o[3], cmake<C>(-c2, s2));    // w^3 (108)
+        ow[4] = cmul(o[4], cmake<C>(-c1, s1));    // w^4 (144)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            a[k] = cadd(e[k], ow[k]);
+            a[k + 5] = csub(e[k], ow[k]);
         }
     }
 };

@@ -50,9 +50,9 @@ template <int N, int T, class P = FftPlan<N>> constexpr bool plan_ok() {
         if ((N / P::R[j]) % T || (N / T) % P::R[j]) return false;
     return true;
 }
-// the plan of a variant: the default one, or the 4-points-per-thread one
-template <int N, bool FOUR> struct PlanSel { using type = FftPlan<N>; };
-template <int N> struct PlanSel<N, true> { using type = Plan4<N>; };
+// the plan of a variant: the default one, or the few-points-per-thread one
+template <int N, bool SMALL> struct PlanSel { using type = FftPlan<N>; };
+template <int N> struct PlanSel<N, true> { using type = typename SmallPlan<N>::type; };
 template <int N> constexpr int half_t() {
     constexpr int T = FftPlan<N>::T;
     return (T % 2 == 0 && 2 * N / T <= 16 && plan_ok<N, T / 2>()) ? T / 2 : T;
@@ -66,8 +66,12 @@ constexpr int cg_fit(size_t per_comp) { return 4 * per_comp <= LDS_CAP ? 4 : (2 
 
 // waves per SIMD the compiler is asked to fit (0: no hint)
 template <class R, int N, int V> struct RowVar {
-    static constexpr bool FOUR = V == 3 && has_plan4<N>();
-    using PL = typename PlanSel<N, FOUR>::type;
+    // v3: the few-points-per-thread plan; for the mixed-radix lengths v2 too,
+    // with the stage epilogue streamed point by point (STREAM: fewer live
+    // registers where the classic epilogue spills)
+    static constexpr bool SMALL = (V == 3 && has_small_plan<N>()) || (V == 2 && has_plans<N>());
+    static constexpr bool STREAM = V == 2 && has_plans<N>();
+    using PL = typename PlanSel<N, SMALL>::type;
     static constexpr int T = PL::T;
     static constexpr int ROWS = imax(1, (V == 2 ? 128 : 256) / T);
     static constexpr int THREADS = T * ROWS;
@@ -82,10 +86,10 @@ template <class R, int N, int V> struct RowVar {
 template <class R, int N, int V> struct ColVar {
     // columns per block: a full 128-byte line (WANT) capped at 512 threads, or
     // narrower tiles (more, smaller blocks per CU; the host then groups the
-    // tiles of one line on one XCD); v2 uses the 4-points-per-thread plan
+    // tiles of one line on one XCD); v2 uses the few-points-per-thread plan
     static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;
-    static constexpr bool FOUR = V == 2 && has_plan4<N>();
-    using PL = typename PlanSel<N, FOUR>::type;
+    static constexpr bool SMALL = V == 2 && has_small_plan<N>();
+    using PL = typename PlanSel<N, SMALL>::type;
     static constexpr int T = PL::T;
     static constexpr int W0 = imax(1, imin(WANT, 512 / T));
     static constexpr int W = (V == 0 || V == 2) ? W0 : imax(1, WANT / 4);
@@ -248,105 +252,180 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 sh_wc[q] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
             }
             if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
-            // state loads are independent of the barrier below: issue them first
-            C yi[4][E];
-            load(MODE == ROW_RHS ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
-            __syncthreads();
-            // field A_mu on this line's points
-            R A[4][E];
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int m = 0; m < E; ++m) A[mu][m] = (R)0;
-#pragma unroll
-            for (int j = 0; j < MAX_TERMS; ++j) {
-                if (j < nterm) {
-                    const R fyz = sh_fyz[line][j];
-                    gptr<const R> tab = rtab + sh_tab[j] + t;
-                    const int mu = sh_mu[j];
-#pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        const R f = fyz * tab[T * m];
-                        A[0][m] += mu == 0 ? f : (R)0;
-                        A[1][m] += mu == 1 ? f : (R)0;
-                        A[2][m] += mu == 2 ? f : (R)0;
-                        A[3][m] += mu == 3 ? f : (R)0;
-                    }
-                }
-            }
-            const long long phx = S->ph + t;
-            const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
-            const C phyz = sh_phyz[line];
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const C ph = cmul(gload<C>(ctab, phx + T * m), phyz);
-                C sv[4], vs[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sv[q] = cadd(yi[q][m], cmul(wc[q], ph));
-                apply_pot(sv, vs, A[0][m], A[1][m], A[2][m], A[3][m]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));   // v = k
-            }
-            if constexpr (MODE == ROW_RHS) {
-                store(a.dst, v);
-                return;
-            } else {
+            if constexpr (VC::STREAM && MODE == ROW_STAGE) {
+                // point by point: the stage input, the RK4 operands and the
+                // outputs of one point are loaded, combined and stored before
+                // the next, so only the transform array stays live
+                __syncthreads();
                 const R h = (R)(-a.dt);
-                const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0);
-                // Classical RK4 with the accumulator written once: with the stage
-                // inputs y_2 = y + h/2 k1, y_3 = y + h/2 k2, y_4 = y + h k3,
-                //   y_{n+1} = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
-                //           = (y_2 + 2 y_3 - y)/3 + y_4/3 + h/6 k4,
-                // so stage 1 stores acc = (y_2 + 2 y_3 - y)/3 and stage 3 finishes.
-                if constexpr (STAGE == 0) {
+                const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0), third = (R)(1.0 / 3.0);
+                const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
+                const C phyz = sh_phyz[line];
+                const long long mask = S->mask;
+                const R myz = mask >= 0 ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
+                gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base + t;
+                gptr<const nv2<R>> py = cview<R>(S->buf[BUF_Y]) + base + t;
+                gptr<const nv2<R>> pacc = cview<R>(S->buf[BUF_ACC]) + base + t;
+                gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base + t;
+                gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base + t;
+                gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base + t;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                for (int m = 0; m < E; ++m) {
+                    R A[4] = {(R)0, (R)0, (R)0, (R)0};
 #pragma unroll
-                        for (int m = 0; m < E; ++m) v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));   // y_2
-                    store(BUF_YS, v);
-                } else if constexpr (STAGE == 1) {
-                    const R third = (R)(1.0 / 3.0);
-                    C y0[4][E], acc[4][E];
-                    load(BUF_Y, y0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int m = 0; m < E; ++m) {
-                            const C y3 = cadd(y0[q][m], cscale(v[q][m], h2));
-                            acc[q][m] = cscale(csub(cadd(yi[q][m], cscale(y3, (R)2)), y0[q][m]), third);
-                            v[q][m] = y3;
-                        }
-                    store(BUF_ACC, acc);
-                    store(BUF_YS, v);
-                } else if constexpr (STAGE == 2) {
-                    C y0[4][E];
-                    load(BUF_Y, y0);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int m = 0; m < E; ++m) v[q][m] = cadd(y0[q][m], cscale(v[q][m], h));   // y_4
-                    store(BUF_YS, v);
-                } else {
-                    const R third = (R)(1.0 / 3.0);
-                    C acc[4][E];
-                    load(BUF_ACC, acc);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int m = 0; m < E; ++m)
-                            v[q][m] = cadd(cadd(acc[q][m], cscale(yi[q][m], third)), cscale(v[q][m], h6));
-                    const long long mask = S->mask;
-                    if (mask >= 0) {
-                        const R myz = rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
-#pragma unroll
-                        for (int m = 0; m < E; ++m) {
-                            const R mk = rtab[mask + t + T * m] * myz;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) v[q][m] = cscale(v[q][m], mk);
+                    for (int j = 0; j < MAX_TERMS; ++j) {
+                        if (j < nterm) {
+                            const R f = sh_fyz[line][j] * rtab[sh_tab[j] + t + T * m];
+                            const int mu = sh_mu[j];
+                            A[0] += mu == 0 ? f : (R)0;
+                            A[1] += mu == 1 ? f : (R)0;
+                            A[2] += mu == 2 ? f : (R)0;
+                            A[3] += mu == 3 ? f : (R)0;
                         }
                     }
-                    store(BUF_Y, v);
+                    const C ph = cmul(gload<C>(ctab, S->ph + t + T * m), phyz);
+                    const long long o = (long long)T * m;
+                    C yi[4], sv[4], vs[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        yi[q] = gload<C>(pin, q * ns + o);
+                        sv[q] = cadd(yi[q], cmul(wc[q], ph));
+                    }
+                    apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
+                    const R mk = (STAGE == 3 && mask >= 0) ? rtab[mask + t + T * m] * myz : (R)1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const C k = cadd(v[q][m], cmul_mi(vs[q]));
+                        C out;
+                        if constexpr (STAGE == 0) {
+                            out = cadd(yi[q], cscale(k, h2));                                   // y_2
+                            if (act) gstore<C>(wys, q * ns + o, out);
+                        } else if constexpr (STAGE == 1) {
+                            const C y0 = gload<C>(py, q * ns + o);
+                            out = cadd(y0, cscale(k, h2));                                      // y_3
+                            const C acc = cscale(csub(cadd(yi[q], cscale(out, (R)2)), y0), third);
+                            if (act) {
+                                gstore<C>(wacc, q * ns + o, acc);
+                                gstore<C>(wys, q * ns + o, out);
+                            }
+                        } else if constexpr (STAGE == 2) {
+                            const C y0 = gload<C>(py, q * ns + o);
+                            out = cadd(y0, cscale(k, h));                                       // y_4
+                            if (act) gstore<C>(wys, q * ns + o, out);
+                        } else {
+                            const C acc = gload<C>(pacc, q * ns + o);
+                            out = cscale(cadd(cadd(acc, cscale(yi[q], third)), cscale(k, h6)), mk);
+                            if (act) gstore<C>(wy, q * ns + o, out);
+                        }
+                        v[q][m] = out;
+                    }
+                    // keep the scheduler from hoisting the next point's loads
+                    // above this one (that would bring back the whole arrays)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            } else {
+                // state loads are independent of the barrier below: issue them first
+                C yi[4][E];
+                load(MODE == ROW_RHS ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
+                __syncthreads();
+                // field A_mu on this line's points
+                R A[4][E];
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                    for (int m = 0; m < E; ++m) A[mu][m] = (R)0;
+#pragma unroll
+                for (int j = 0; j < MAX_TERMS; ++j) {
+                    if (j < nterm) {
+                        const R fyz = sh_fyz[line][j];
+                        gptr<const R> tab = rtab + sh_tab[j] + t;
+                        const int mu = sh_mu[j];
+#pragma unroll
+                        for (int m = 0; m < E; ++m) {
+                            const R f = fyz * tab[T * m];
+                            A[0][m] += mu == 0 ? f : (R)0;
+                            A[1][m] += mu == 1 ? f : (R)0;
+                            A[2][m] += mu == 2 ? f : (R)0;
+                            A[3][m] += mu == 3 ? f : (R)0;
+                        }
+                    }
+                }
+                const long long phx = S->ph + t;
+                const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
+                const C phyz = sh_phyz[line];
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const C ph = cmul(gload<C>(ctab, phx + T * m), phyz);
+                    C sv[4], vs[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sv[q] = cadd(yi[q][m], cmul(wc[q], ph));
+                    apply_pot(sv, vs, A[0][m], A[1][m], A[2][m], A[3][m]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));   // v = k
+                }
+                if constexpr (MODE == ROW_RHS) {
+                    store(a.dst, v);
+                    return;
+                } else {
+                    const R h = (R)(-a.dt);
+                    const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0);
+                    // Classical RK4 with the accumulator written once: with the stage
+                    // inputs y_2 = y + h/2 k1, y_3 = y + h/2 k2, y_4 = y + h k3,
+                    //   y_{n+1} = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
+                    //           = (y_2 + 2 y_3 - y)/3 + y_4/3 + h/6 k4,
+                    // so stage 1 stores acc = (y_2 + 2 y_3 - y)/3 and stage 3 finishes.
+                    if constexpr (STAGE == 0) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int m = 0; m < E; ++m) v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));   // y_2
+                        store(BUF_YS, v);
+                    } else if constexpr (STAGE == 1) {
+                        const R third = (R)(1.0 / 3.0);
+                        C y0[4][E], acc[4][E];
+                        load(BUF_Y, y0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int m = 0; m < E; ++m) {
+                                const C y3 = cadd(y0[q][m], cscale(v[q][m], h2));
+                                acc[q][m] = cscale(csub(cadd(yi[q][m], cscale(y3, (R)2)), y0[q][m]), third);
+                                v[q][m] = y3;
+                            }
+                        store(BUF_ACC, acc);
+                        store(BUF_YS, v);
+                    } else if constexpr (STAGE == 2) {
+                        C y0[4][E];
+                        load(BUF_Y, y0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int m = 0; m < E; ++m) v[q][m] = cadd(y0[q][m], cscale(v[q][m], h));   // y_4
+                        store(BUF_YS, v);
+                    } else {
+                        const R third = (R)(1.0 / 3.0);
+                        C acc[4][E];
+                        load(BUF_ACC, acc);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int m = 0; m < E; ++m)
+                                v[q][m] = cadd(cadd(acc[q][m], cscale(yi[q][m], third)), cscale(v[q][m], h6));
+                        const long long mask = S->mask;
+                        if (mask >= 0) {
+                            const R myz = rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
+#pragma unroll
+                            for (int m = 0; m < E; ++m) {
+                                const R mk = rtab[mask + t + T * m] * myz;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) v[q][m] = cscale(v[q][m], mk);
+                            }
+                        }
+                        store(BUF_Y, v);
+                    }
+                }
+            }
+            if constexpr (MODE == ROW_STAGE) {
                 // forward x transform of the next stage's input
                 fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
                 store(BUF_T, v);
