@@ -164,6 +164,23 @@ enum {
  * (2 pi)^(3-d) delta_perp(p + q - k), no phase-space or e^2 factors (Fig. 7). */
 swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]);
 
+/* Pair-amplitude matrix, eq. (Nmn) for every pair at once: out[2*(m*nv + n)],
+ * out[2*(m*nv + n) + 1] = re, im of Omega(u_solves[m], v_solves[n]) in form 1
+ * or 2, the same value swf_amplitude(SWF_AMP_PAIR1/2) returns for that pair.
+ * Both inner products are evaluated as dense complex contractions over all
+ * sites and spinor components (the background overlap in x space, the
+ * projected one in k space), so every state is read once for the whole
+ * matrix instead of once per pair; they run on the FP64 matrix cores with
+ * FP64 accumulation in either precision.
+ * Requirements: at t_in (SWF_E_ORDER otherwise); every u_solves[m] a U solve
+ * and every v_solves[n] a V solve, all on one grid, and p_perp + q_perp = 0 on
+ * the trivial axes for every pair (SWF_E_ARG otherwise).  out: caller-owned,
+ * 2 * nu * nv doubles.  The first call (or a larger matrix) allocates device
+ * scratch owned by the context.  Overwrites the solves' FFT buffers (like
+ * swf_amplitude), not their states. */
+swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
+                           double* out);
+
 enum {
     SWF_P_MARGINAL_E = 0,   /* electron marginal (U_s|Pi_-|U_s) of U solve i           */
     SWF_P_MARGINAL_POS = 1, /* positron marginal (V_s|Pi_+|V_s) of V solve i           */

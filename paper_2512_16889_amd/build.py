@@ -39,7 +39,7 @@ def source_hash() -> str:
 
 def _jobs():
     units = [("swf_api.cpp", [], "swf_api.o"), ("swf_table.cpp", [], "swf_table.o"),
-             ("swf_reduce.hip", [], "swf_reduce.o")]
+             ("swf_reduce.hip", [], "swf_reduce.o"), ("swf_pair.hip", [], "swf_pair.o")]
     for real, tag in (("float", "f32"), ("double", "f64")):
         for g in range(N_GROUPS):
             units.append(("swf_sizes.hip", [f"-DSWF_REAL={real}", f"-DSWF_TAG={tag}", f"-DSWF_GROUP={g}"],

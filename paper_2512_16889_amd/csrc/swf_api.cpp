@@ -491,6 +491,8 @@ struct swf_ctx {
     int step = 0;
     bool t_valid = true;
     size_t lds_max = 65536;       // dynamic LDS one workgroup may use on this device
+    void* pm_buf = nullptr;       // pair-matrix scratch (grown on demand, freed by swf_free)
+    size_t pm_bytes = 0;
     std::vector<char> kvalid;
     std::vector<int> bw_done;
     std::vector<cd> bw_cache;     // 3 terms finite + 3 past per vertex
@@ -1046,6 +1048,115 @@ static int pair_amp(swf_ctx* ctx, int i, int j, int form, cd& out) {
     return SWF_OK;
 }
 
+// ------------------------------------------------------------ pair matrix
+// G[m][n] = sum_K conj(A_m[K]) B_n[K] over sites and spinor components, every
+// A_m from rows `ra` and B_n from `rb` (PG_STATE rows: the solves' buffer
+// `role`; PG_BKG rows: their background plane-wave spinors), optionally with
+// Pi_sign applied to k-space states.  Result: na x nb, row-major.
+static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int arole, const std::vector<int>& rb,
+                     int bsrc, int brole, int proj, std::vector<cd>& out) {
+    const int s0 = ra[0];
+    const swf_grid& G = ctx->P.grids[ctx->P.solves[s0].grid];
+    const long long ns = ctx->P.hs[s0].nsites;
+    const int na = (int)ra.size(), nb = (int)rb.size();
+    swf::PairArgs a;
+    memset(&a, 0, sizeof(a));
+    a.tiles_m = (na + 31) / 32;
+    a.tiles_n = (nb + 31) / 32;
+    a.mp = 32 * a.tiles_m;
+    a.np = 32 * a.tiles_n;
+    const long long chunks = (ns + 7) / 8;
+    const long long want = std::max(1LL, 1024LL / (a.tiles_m * a.tiles_n));
+    a.splits = (int)std::min(chunks, want);
+    a.per = ((chunks + a.splits - 1) / a.splits) * 8;
+    a.splits = (int)((ns + a.per - 1) / a.per);
+    a.ns = ns;
+    a.dim = G.dim;
+    for (int j = 0; j < 3; ++j) {
+        a.x0[j] = j < G.dim ? -0.5 * G.L[j] : 0.0;
+        a.dx[j] = j < G.dim ? G.L[j] / G.n[j] : 0.0;
+    }
+    a.proj = proj;
+    // scratch: row descriptors, then the partial tiles and their sum
+    const size_t ops_bytes = align256(sizeof(swf::PairOp) * (na + nb));
+    const size_t part_bytes = sizeof(double2) * (size_t)(a.splits + 1) * a.mp * a.np;
+    const size_t need = ops_bytes + part_bytes;
+    if (need > ctx->pm_bytes) {
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        if (ctx->pm_buf) HIPCHK(hipFree(ctx->pm_buf));
+        ctx->pm_buf = nullptr;
+        ctx->pm_bytes = 0;
+        HIPCHK(hipMalloc(&ctx->pm_buf, need));
+        ctx->pm_bytes = need;
+    }
+    std::vector<swf::PairOp> ops(na + nb);
+    auto fill = [&](const std::vector<int>& rows, swf::PairOp* o) {
+        for (size_t r = 0; r < rows.size(); ++r) {
+            const swf_solve& sv = ctx->P.solves[rows[r]];
+            o[r].solve = rows[r];
+            o[r].pad = 0;
+            // background plane wave exp(i K.x): K = p for U, -q for V
+            for (int j = 0; j < 3; ++j) o[r].K[j] = sv.kind == 0 ? sv.p[j] : -sv.p[j];
+        }
+    };
+    fill(ra, ops.data());
+    fill(rb, ops.data() + na);
+    swf::PairOp* d_ops = (swf::PairOp*)ctx->pm_buf;
+    a.part = (double2*)((char*)ctx->pm_buf + ops_bytes);
+    a.solves = ctx->d_solves();
+    a.a = swf::PairSide{d_ops, na, asrc, arole};
+    a.b = swf::PairSide{d_ops + na, nb, bsrc, brole};
+    HIPCHK(hipMemcpyAsync(d_ops, ops.data(), sizeof(swf::PairOp) * ops.size(), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(swf::launch_pair_gemm(ctx->P.fp64, a, ctx->st));
+    std::vector<double2> h((size_t)a.mp * a.np);
+    HIPCHK(hipMemcpyAsync(h.data(), a.part + (size_t)a.splits * a.mp * a.np, sizeof(double2) * h.size(),
+                          hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    out.resize((size_t)na * nb);
+    for (int m = 0; m < na; ++m)
+        for (int n = 0; n < nb; ++n) out[(size_t)m * nb + n] = cd(h[(size_t)m * a.np + n].x, h[(size_t)m * a.np + n].y);
+    return SWF_OK;
+}
+
+// Omega(m, n) of eq. (Nmn) for every pair: the direct overlap with the
+// background as one x-space contraction, the projected overlap as one
+// k-space contraction, combined with the time phase and dV (dV/N for k space).
+static int pair_matrix(swf_ctx* ctx, int form, const std::vector<int>& us, const std::vector<int>& vs,
+                       std::vector<cd>& out) {
+    for (int u : us) {
+        int r = check_pair(ctx, u, vs[0]);
+        if (r) return r;
+    }
+    for (int v : vs) {
+        int r = check_pair(ctx, us[0], v);
+        if (r) return r;
+    }
+    for (int s : us) {
+        int r = kspace(ctx, s);
+        if (r) return r;
+    }
+    for (int s : vs) {
+        int r = kspace(ctx, s);
+        if (r) return r;
+    }
+    std::vector<cd> gk, gx;
+    int r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_T, vs, swf::PG_STATE, swf::BUF_T, form == 1 ? +1 : -1, gk);
+    if (r) return r;
+    if (form == 1) r = pair_gemm(ctx, us, swf::PG_BKG, 0, vs, swf::PG_STATE, swf::BUF_Y, 0, gx);
+    else r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_Y, vs, swf::PG_BKG, 0, 0, gx);
+    if (r) return r;
+    const double tin = ctx->P.win.t_in;
+    const double dV = ctx->P.hs[us[0]].dV, inv_n = ctx->P.hs[us[0]].inv_n;
+    const size_t nu = us.size(), nv = vs.size();
+    out.resize(nu * nv);
+    for (size_t m = 0; m < nu; ++m)
+        for (size_t n = 0; n < nv; ++n) {
+            const cd ph = form == 1 ? std::polar(1.0, ctx->P.hs[us[m]].E * tin) : std::polar(1.0, -ctx->P.hs[vs[n]].E * tin);
+            out[m * nv + n] = dV * ph * gx[m * nv + n] + dV * inv_n * gk[m * nv + n];
+        }
+    return SWF_OK;
+}
+
 // Breit-Wheeler amplitude terms of vertex v at t_in.
 static int bw_terms(swf_ctx* ctx, int v) {
     if (ctx->bw_done[v]) return SWF_OK;
@@ -1382,6 +1493,34 @@ swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]) {
     return std::isfinite(out[0]) && std::isfinite(out[1]) ? SWF_OK : SWF_E_NONFINITE;
 }
 
+swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
+                           double* out) {
+    if (!ctx || !out || !u_solves || !v_solves || nu <= 0 || nv <= 0) return SWF_E_ARG;
+    if (form != 1 && form != 2) {
+        ctx->err = "form must be 1 or 2";
+        return SWF_E_ARG;
+    }
+    if (ctx->step != ctx->P.steps) {
+        ctx->err = "amplitudes are defined at t_in: step to the end first";
+        return SWF_E_ORDER;
+    }
+    int r = enter(ctx);
+    if (r) return (swf_status)r;
+    std::vector<int> us(u_solves, u_solves + nu), vs(v_solves, v_solves + nv);
+    std::vector<cd> res;
+    r = pair_matrix(ctx, form, us, vs, res);
+    if (r) return (swf_status)r;
+    r = leave(ctx);
+    if (r) return (swf_status)r;
+    bool finite = true;
+    for (size_t k = 0; k < res.size(); ++k) {
+        out[2 * k] = res[k].real();
+        out[2 * k + 1] = res[k].imag();
+        finite = finite && std::isfinite(out[2 * k]) && std::isfinite(out[2 * k + 1]);
+    }
+    return finite ? SWF_OK : SWF_E_NONFINITE;
+}
+
 swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out) {
     if (!ctx || !out) return SWF_E_ARG;
     if (ctx->step != ctx->P.steps) {
@@ -1604,6 +1743,7 @@ void swf_free(swf_ctx* ctx) {
     if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) hipGraphDestroy(ctx->graph);
     if (ctx->own_arena && ctx->arena) hipFree(ctx->arena);
+    if (ctx->pm_buf) hipFree(ctx->pm_buf);
     if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) hipEventDestroy(ctx->ev_out);
     if (ctx->st) hipStreamDestroy(ctx->st);

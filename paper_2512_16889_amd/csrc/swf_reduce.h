@@ -40,7 +40,34 @@ struct BwArgs {
     double2* M;          // [vertex][3] accumulated integrals (device, double)
 };
 
+// Pair-amplitude matrix contraction G[m][n] = sum_K conj(A_m[K]) B_n[K].
+enum { PG_STATE = 0, PG_BKG = 1 };
+struct PairOp {
+    int solve;
+    int pad;
+    double K[3];         // PG_BKG: plane-wave momentum on the lattice axes (w e^{i K.x})
+};
+struct PairSide {
+    const PairOp* ops;   // one per row (side a) or column (side b)
+    int n;
+    int src;             // PG_STATE: the state array of buffer role `role`; PG_BKG: background
+    int role;
+};
+struct PairArgs {
+    const SolveDev* solves;
+    PairSide a, b;
+    int proj;            // 0, or +1 / -1: Pi_+ / Pi_- of k-space states on both sides
+    long long ns;        // sites of the (common) lattice
+    int dim;
+    double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
+    int tiles_m, tiles_n, splits;
+    long long per;       // sites per split (a multiple of the staging chunk)
+    int mp, np;          // padded output dimensions (multiples of 32)
+    double2* part;       // [mp][np][splits] partial tiles, then [mp][np] the sum
+};
+
 hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
+hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
 hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_tick(int* step, hipStream_t st);

@@ -87,6 +87,8 @@ _lib.swf_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_longlong), _P(C.c_
 _lib.swf_reset_stats.argtypes = [C.c_void_p]
 _lib.swf_steps.argtypes = [C.c_void_p, _P(C.c_int), _P(C.c_int)]
 _lib.swf_supported_n.argtypes = [C.c_int]
+_lib.swf_pair_matrix.argtypes = [C.c_void_p, C.c_int, _P(C.c_int), C.c_int, _P(C.c_int), C.c_int, _P(C.c_double)]
+_lib.swf_pair_matrix.restype = C.c_int
 _lib.swf_tune_report.argtypes = [C.c_void_p]
 _lib.swf_tune_report.restype = C.c_char_p
 _lib.swf_last_error.argtypes = [C.c_void_p]
@@ -97,7 +99,7 @@ _lib.swf_free.restype = None
 EXPORTED = ["swf_workspace_size", "swf_init", "swf_step", "swf_reset", "swf_sync", "swf_amplitude", "swf_probability",
             "swf_diagnostics", "swf_get_psi", "swf_set_psi", "swf_get_bw_state", "swf_set_bw_state",
             "swf_apply_op", "swf_kernel_stats", "swf_reset_stats", "swf_supported_n", "swf_steps",
-            "swf_tune_report", "swf_last_error", "swf_free"]
+            "swf_tune_report", "swf_last_error", "swf_free", "swf_pair_matrix"]
 
 
 class SwfError(RuntimeError):
@@ -307,6 +309,15 @@ class Context:
         return self._from_lib(out, i)
 
     # ---------------------------------------------------------------- profiling
+    def pair_matrix(self, u_solves, v_solves, form: int = 1):
+        """Omega(u_solves[m], v_solves[n]) for every pair, as an nu x nv complex array."""
+        us = (C.c_int * len(u_solves))(*[int(i) for i in u_solves])
+        vs = (C.c_int * len(v_solves))(*[int(i) for i in v_solves])
+        out = np.zeros(2 * len(u_solves) * len(v_solves), dtype=np.float64)
+        self._check(_lib.swf_pair_matrix(self._ctx, int(form), us, len(u_solves), vs, len(v_solves),
+                                         out.ctypes.data_as(_P(C.c_double))))
+        return (out[0::2] + 1j * out[1::2]).reshape(len(u_solves), len(v_solves))
+
     def kernel_stats(self, kind: int):
         n, ms, by = C.c_longlong(0), C.c_double(0), C.c_double(0)
         self._check(_lib.swf_kernel_stats(self._ctx, kind, C.byref(n), C.byref(ms), C.byref(by)))
