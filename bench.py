@@ -95,9 +95,10 @@ def run_job(ctx, prob):
     return out
 
 
-def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True, chunk=0):
+def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True, chunk=0,
+               variant=None):
     ctx = S.Context(prob, precision=precision, batched=batched, use_graph=graph, profile=profile, tune=tune,
-                    chunk=chunk)
+                    chunk=chunk, variant=variant)
     report = ctx.tune_report()
     results = None
     for _ in range(W):
@@ -170,6 +171,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 per-instance leg")
     ap.add_argument("--chunk", type=int, default=0, help="solves per launch group (0 = all)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile variants")
+    ap.add_argument("--variant", type=int, default=None, help="force tile variant 0..3 for every pass")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -217,7 +219,8 @@ def main():
 
     paths = {}
     wall, P_mixed, stats, tune_rep, norms_m = timed_jobs(S, torch, prob, "mixed", args.steps, args.warmup,
-                                                        chunk=args.chunk, tune=not args.no_tune)
+                                                        chunk=args.chunk, tune=not args.no_tune,
+                                                        variant=args.variant)
     paths["mixed_batched"] = summarize(wall, stats)
     paths["mixed_batched"]["autotune"] = tune_rep
     print(f"[bench] mixed batched: {wall:.2f} s for {args.steps} job(s) -> {paths['mixed_batched']['value']:.4e} "
@@ -225,7 +228,8 @@ def main():
     headline = "mixed_batched"
     if not args.no_fp64:
         wall64, P64, stats64, tune64, norms64 = timed_jobs(S, torch, prob, "fp64", args.steps, args.warmup,
-                                                           chunk=args.chunk, tune=not args.no_tune)
+                                                           chunk=args.chunk, tune=not args.no_tune,
+                                                           variant=args.variant)
         paths["fp64_batched"] = summarize(wall64, stats64)
         paths["fp64_batched"]["autotune"] = tune64
         rel = [abs(a - b) / abs(b) for a, b in zip(P_mixed, P64) if b != 0]
@@ -267,7 +271,8 @@ def main():
     if H["roofline"]["kernel"].startswith("row pass"):
         H["roofline"]["traffic"] = stored_traffic("fp64" if headline.startswith("fp64") else "mixed",
                                                   prob.grids[0].n[0],
-                                                  chosen_row_variant(H.get("autotune") or ""))
+                                                  chosen_row_variant(H.get("autotune") or "")
+                                                  if args.variant is None else args.variant)
     if "fp64_plain_per_instance" in paths:
         out["speedup_vs_fp64_plain"] = H["value"] / paths["fp64_plain_per_instance"]["value"]
     if not args.no_cpu:

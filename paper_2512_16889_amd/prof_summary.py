@@ -5,10 +5,11 @@ prints a markdown table of the per-kernel dispatch statistics.
 
 ``python -m paper_2512_16889_amd.prof_summary traffic <pmc_fetch.csv>
 <pmc_write.csv> <copy_fetch.csv> <copy_write.csv> <copy_bytes>`` prints, as
-JSON, the HBM bytes per dispatch of every kernel in the first two files
-(FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by what the same
-counter reads for a plain device copy of ``copy_bytes`` bytes each way, and the
-sha256 of the kernel sources they were taken from.
+JSON, the HBM bytes per dispatch of every kernel in the first two arguments
+(FETCH_SIZE and WRITE_SIZE, KiB per dispatch; each may be a comma-separated
+list of files, e.g. runs with different tile variants forced), each scaled by
+what the same counter reads for a plain device copy of ``copy_bytes`` bytes
+each way, and the sha256 of the kernel sources they were taken from.
 """
 from __future__ import annotations
 
@@ -33,12 +34,13 @@ def stats_table(path, top=16):
     return "\n".join(out)
 
 
-def _per_kernel(path, counter):
+def _per_kernel(paths, counter):
     acc = {}
-    for r in _rows(path):
-        if r["Counter_Name"] != counter:
-            continue
-        acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+    for path in paths.split(","):
+        for r in _rows(path):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
     return acc
 
 
