@@ -186,7 +186,7 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: every solve of a job is independent and "
+        print(json.dumps({"error": "the solver runs on one GPU only: every solve of a job is independent and "
                           "the multi-GPU sharding is described, not built; run with --gpus 1"}))
         sys.exit(2)
 

@@ -42,7 +42,7 @@ typedef enum {
     SWF_E_NOMEM = 2,       /* device allocation failed or workspace too small       */
     SWF_E_HIP = 3,         /* a HIP runtime call failed                              */
     SWF_E_ORDER = 4,       /* call out of order (e.g. amplitude before t_in)         */
-    SWF_E_UNSUPPORTED = 5, /* grid size / option not supported by this build         */
+    SWF_E_UNSUPPORTED = 5, /* grid size / option the library does not support       */
     SWF_E_NONFINITE = 6    /* a NaN or Inf was detected in the state                 */
 } swf_status;
 
@@ -228,7 +228,7 @@ swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in,
 swf_status swf_kernel_stats(swf_ctx* ctx, int kind, long long* launches, double* ms, double* bytes);
 swf_status swf_reset_stats(swf_ctx* ctx);
 
-/* 1 if n has an FFT plan in this build. */
+/* 1 if the library has an FFT plan for length n. */
 int swf_supported_n(int n);
 
 /* Total steps of the context's window; current step index. */
