@@ -84,23 +84,27 @@ template <class R, int N, int V> struct RowVar {
 };
 
 template <class R, int N, int V> struct ColVar {
-    // columns per block: a full 128-byte line (WANT) capped at 512 threads, or
-    // narrower tiles (more, smaller blocks per CU; the host then groups the
-    // tiles of one line on one XCD); v2 uses the few-points-per-thread plan
+    // columns per block:
+    //   v0: a full 128-byte line (WANT columns) of the default plan, capped at
+    //       512 threads;
+    //   v1: narrower tiles (more, smaller blocks per CU; the host then groups
+    //       the tiles of one line on one XCD);
+    //   v2: the few-points-per-thread plan, capped at 512 threads;
+    //   v3: the few-points-per-thread plan with up to 1024 threads, so that a
+    //       tile still covers a full 128-byte line where T is large (N >= 512)
     static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;
-    static constexpr bool SMALL = V == 2 && has_small_plan<N>();
+    static constexpr bool SMALL = (V == 2 || V == 3) && has_small_plan<N>();
     using PL = typename PlanSel<N, SMALL>::type;
     static constexpr int T = PL::T;
-    static constexpr int W0 = imax(1, imin(WANT, 512 / T));
-    static constexpr int W = (V == 0 || V == 2) ? W0 : imax(1, WANT / 4);
+    static constexpr int W0 = imax(1, imin(WANT, (V == 3 ? 1024 : 512) / T));
+    static constexpr int W = V == 1 ? imax(1, WANT / 4) : W0;
     static constexpr int THREADS = T * W;
     static constexpr size_t PER_COMP = (size_t)N * W * sizeof(cpx<R>);
-    static constexpr int CG = V == 3 ? imin(2, cg_fit(PER_COMP)) : 1;
+    static constexpr int CG = 1;
     static constexpr size_t BYTES = CG * PER_COMP;
     static constexpr bool SEQ = false;
     static_assert(plan_ok<N, T, PL>(), "column variant violates the FFT plan constraints");
 };
-
 
 // Transform the four components of a line: together (shared exchange rounds,
 // more registers live) or one component after another (SEQ: fewer registers,
