@@ -9,7 +9,8 @@ with the state held on chip.  It is checked against:
   counts split over several calls, runs longer than one launch (1024 steps),
   batches of many solves (many workgroups), and observables at t_in;
 * the fallback: a field with more profile tables than fit in LDS next to the
-  state runs on the pass path (no whole-loop launch) with the same result.
+  exchange rows runs on the pass path (no whole-loop launch) with the same
+  result.
 FP64 to 1e-10 relative against the oracle; mixed precision to 2e-5 (FP32
 state, about 100 steps).
 """
@@ -146,9 +147,12 @@ def test_line_kernel_batch_many_solves(S):
 
 
 def test_line_kernel_lds_fallback(S):
-    # five profile tables of 1024 doubles do not fit next to the FP64 state:
-    # the context runs the pass path instead, with the oracle's result
+    # eight profile tables of 1024 doubles do not fit in LDS next to the FP64
+    # exchange rows: the context runs the pass path instead, with the oracle's result
     prob = line_problem(1024, nterm=5, t_half=1.0)
+    extra = [W.Term(0, 0.05 * (j + 1), W.gauss(1.0 + 0.2 * j), [W.sech2(8.0 + j), W.const(), W.const()])
+             for j in range(3)]
+    prob.fields = [list(prob.fields[0]) + extra]
     with S.Context(prob, precision="fp64", profile=True) as ctx:
         ctx.step()
         ctx.sync()
