@@ -12,7 +12,10 @@ Each test ties the oracle to an independent statement:
   independent integrator and an independently written Hamiltonian) gives the
   same marginal and pair amplitude;
 * charge-conjugation + reflection symmetry of the spectrum;
-* RK4 converges at order 4 in dt.
+* RK4 converges at order 4 in dt;
+* a 90-degree rotation of field and momentum on a square lattice leaves the
+  spin-summed marginal unchanged;
+* summed over every lattice mode, electrons and positrons balance.
 """
 import numpy as np
 import pytest
@@ -212,3 +215,78 @@ def test_marginal_resolves_tiny_negative_energy_content():
     total = sv.lat.dV / n * np.sum(np.abs(a) ** 2 + np.abs(b) ** 2)
     assert total / want > 1e11
     assert ob.marginal(sv, psi) == pytest.approx(want, rel=1e-6)
+
+
+def _reflected(pr):
+    """The profile of s -> f(-s) for an even envelope (gauss, sech2, const)."""
+    assert pr.type in (W.PROF_CONST, W.PROF_GAUSS, W.PROF_SECH2)
+    return W.Profile(pr.type, -pr.c, pr.w, pr.k, -pr.phi)
+
+
+def _rotated_field(terms):
+    """R A for the 90-degree rotation R (x, y) -> (-y, x) about z: A_0 and A_3
+    are scalars under R, (A_1, A_2) -> (-A_2, A_1), all at the point R^-1 x =
+    (y, -x)."""
+    out = []
+    for tm in terms:
+        fx = [_reflected(tm.fx[1]), tm.fx[0], tm.fx[2]]          # f(R^-1 x) = f_x(y) f_y(-x) f_z(z)
+        mu, amp = {0: (0, tm.amp), 1: (2, tm.amp), 2: (1, -tm.amp), 3: (3, tm.amp)}[tm.mu]
+        out.append(W.Term(mu, amp, tm.ft, fx))
+    return out
+
+
+def test_rotation_by_90_degrees_maps_the_spectrum():
+    # square periodic lattice: the rotation maps lattice points to lattice
+    # points, so the spin-summed marginal obeys P(p; A) = P(R p; R A).  What
+    # can break it on the lattice: the Nyquist mode (wavenumber -pi/dx, not
+    # +pi/dx) and the box edge (-L/2 is a lattice point, +L/2 is not), so the
+    # grid is fine enough and every profile negligible at the edge.  Every
+    # coupling is on (A_0, A_1, A_2, A_3), with off-centre profiles and
+    # carriers, so a swapped axis or a wrong sign in alpha^j breaks it.
+    n, L = 64, 24.0
+    F = [W.Term(1, 0.9, W.sech2(1.2), [W.gauss(2.5, c=0.7), W.sech2(1.2, c=-0.4), W.const()]),
+         W.Term(2, 0.6, W.gauss(1.0, c=0.2), [W.sech2(1.5, c=0.3, k=0.5, phi=0.2), W.gauss(2.0), W.const()]),
+         W.Term(0, 0.4, W.gauss(1.3, k=0.7), [W.gauss(2.2, c=-0.6), W.gauss(2.4, c=0.5), W.const()]),
+         W.Term(3, 0.3, W.sech2(0.9), [W.gauss(2.5), W.sech2(1.0, c=0.9), W.const()])]
+    p = [0.45, -0.3, 0.2]
+    Rp = [-p[1], p[0], p[2]]
+    g = W.Grid(2, [n, n, 1], [L, L, 1])
+    win = W.Window(-2.5, 2.5, 0.05)
+    P = []
+    for field, mom in ((F, p), (_rotated_field(F), Rp)):
+        prob = W.Problem("rot", [g], [field], [W.Solve(0, 1, mom), W.Solve(0, -1, mom)], win)
+        P.append(sum(ob.marginal(SWFSolve(prob, i), SWFSolve(prob, i).run()) for i in range(2)))
+    assert P[0] > 1e-6
+    assert P[1] == pytest.approx(P[0], rel=1e-8)
+    # and a rotation that is not a symmetry of the field changes it
+    prob = W.Problem("rot", [g], [F], [W.Solve(0, 1, Rp), W.Solve(0, -1, Rp)], win)
+    Pwrong = sum(ob.marginal(SWFSolve(prob, i), SWFSolve(prob, i).run()) for i in range(2))
+    assert abs(Pwrong - P[0]) > 1e-3 * P[0]
+
+
+def test_charge_balance_over_all_lattice_modes():
+    # every created electron has a positron partner: summed over all lattice
+    # momenta and spins, sum P_e(s, p) = sum P_pos(r, q) with q_perp = -p_perp
+    # (exact for unitary evolution; RK4 is unitary to O(dt^4)).  An odd
+    # number of points has no Nyquist mode, whose wavenumber the lattice
+    # derivative takes as -pi/dx for both signs of the background momentum.
+    n, L, pperp = 15, 15.0, 0.3
+    solves = []
+    for kx in range(-(n // 2), n // 2 + 1):
+        px = 2 * np.pi * kx / L
+        for s in (1, -1):
+            solves.append(W.Solve(0, s, [px, pperp, 0.0]))
+            solves.append(W.Solve(1, s, [px, -pperp, 0.0]))
+    F = [W.Term(1, 1.3, W.sech2(1.0), [W.sech2(2.0), W.const(), W.const()]),
+         W.Term(0, 0.5, W.gauss(0.8), [W.gauss(1.5, c=0.4), W.const(), W.const()])]
+    prob = W.Problem("cb", [W.Grid(1, [n, 1, 1], [L, 1, 1])], [F], solves, W.Window(-6.0, 6.0, 0.01))
+    Pe = Pp = 0.0
+    for i, sv in enumerate(prob.solves):
+        svv = SWFSolve(prob, i)
+        P = ob.marginal(svv, svv.run())
+        if sv.kind == 0:
+            Pe += P
+        else:
+            Pp += P
+    assert Pe > 1e-4
+    assert Pp == pytest.approx(Pe, rel=1e-6)
