@@ -85,8 +85,16 @@ def stored_traffic(precision, n, variant):
     return sum(per_stage) / 4
 
 
-def run_job(ctx, prob):
-    ctx.step()
+def run_job(ctx, prob, progress=0):
+    if progress > 0:
+        # chunks of `progress` steps, each synchronised and reported (long jobs)
+        left = prob.window.steps
+        while left > 0:
+            left = ctx.step(min(progress, left))
+            ctx.sync()
+            print(f"[bench]   {prob.window.steps - left}/{prob.window.steps} steps", file=sys.stderr, flush=True)
+    else:
+        ctx.step()
     out = []
     for i, s in enumerate(prob.solves):
         out.append(ctx.marginal(i))
@@ -96,21 +104,21 @@ def run_job(ctx, prob):
 
 
 def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True, chunk=0,
-               variant=None):
+               variant=None, progress=0):
     ctx = S.Context(prob, precision=precision, batched=batched, use_graph=graph, profile=profile, tune=tune,
                     chunk=chunk, variant=variant)
     report = ctx.tune_report()
     results = None
     for _ in range(W):
         ctx.reset()
-        run_job(ctx, prob)
+        run_job(ctx, prob, progress)
     ctx.sync()
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
         ctx.reset()
-        results = run_job(ctx, prob)
+        results = run_job(ctx, prob, progress)
     ctx.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -172,6 +180,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="solves per launch group (0 = all)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile variants")
     ap.add_argument("--variant", type=int, default=None, help="force tile variant 0..3 for every pass")
+    ap.add_argument("--progress", type=int, default=0, metavar="STEPS",
+                    help="step in synchronised chunks of STEPS and report each (long jobs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -220,7 +230,7 @@ def main():
     paths = {}
     wall, P_mixed, stats, tune_rep, norms_m = timed_jobs(S, torch, prob, "mixed", args.steps, args.warmup,
                                                         chunk=args.chunk, tune=not args.no_tune,
-                                                        variant=args.variant)
+                                                        variant=args.variant, progress=args.progress)
     paths["mixed_batched"] = summarize(wall, stats)
     paths["mixed_batched"]["autotune"] = tune_rep
     print(f"[bench] mixed batched: {wall:.2f} s for {args.steps} job(s) -> {paths['mixed_batched']['value']:.4e} "
@@ -229,7 +239,7 @@ def main():
     if not args.no_fp64:
         wall64, P64, stats64, tune64, norms64 = timed_jobs(S, torch, prob, "fp64", args.steps, args.warmup,
                                                            chunk=args.chunk, tune=not args.no_tune,
-                                                           variant=args.variant)
+                                                           variant=args.variant, progress=args.progress)
         paths["fp64_batched"] = summarize(wall64, stats64)
         paths["fp64_batched"]["autotune"] = tune64
         rel = [abs(a - b) / abs(b) for a, b in zip(P_mixed, P64) if b != 0]
