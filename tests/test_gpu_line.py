@@ -159,3 +159,31 @@ def test_line_kernel_lds_fallback(S):
         assert whole_loop_launches(ctx) == 0
         for i in range(len(prob.solves)):
             assert relerr(ctx.get_psi(i), SWFSolve(prob, i).run()) < 1e-10
+
+
+def test_line_kernel_not_used_when_a_grid_is_not_1d(S):
+    # one 1D and one 2D grid in the same context: the whole-loop path needs
+    # every grid to be 1D, so both run on the pass path, with the oracle's result
+    g1 = W.Grid(1, [64, 1, 1], [38.4, 1.0, 1.0])
+    g2 = W.Grid(2, [32, 32, 1], [30.0, 30.0, 1.0])
+    prob = W.Problem("mixdim", [g1, g2], [field_mix(1)[:3], field_mix(2)],
+                     [W.Solve(0, 1, [0.3, 0.2, -0.1], 0, 0), W.Solve(1, -1, [0.2, -0.3, 0.1], 1, 1)],
+                     W.Window(-1.5, 1.5, 0.05))
+    with S.Context(prob, precision="fp64", profile=True) as ctx:
+        ctx.step()
+        ctx.sync()
+        assert whole_loop_launches(ctx) == 0
+        for i in range(len(prob.solves)):
+            assert relerr(ctx.get_psi(i), SWFSolve(prob, i).run()) < 1e-10
+
+
+def test_line_kernel_with_graph_option(S):
+    # use_graph captures the pass path's step; a 1D problem still runs the
+    # whole-loop kernel and gives the same states
+    prob = line_problem(128, nterm=3, n_mom=2)
+    with S.Context(prob, precision="fp64", use_graph=True) as g, S.Context(prob, precision="fp64") as e:
+        for c in (5, 17, 58):
+            g.step(c)
+            e.step(c)
+            for i in range(len(prob.solves)):
+                assert np.array_equal(g.get_psi(i), e.get_psi(i))
