@@ -25,7 +25,10 @@ strong-field processes in multidimensional background fields"):
                   overlap of eq. (Mabfinite) integrated as an augmented
                   state (the Y = (psi, M) construction of the BW numerical
                   section) plus the analytic asymptotic-past terms
-                  (eq. (MScatScatPast) and its two single-mode partners).
+                  (eq. (MScatScatPast) and its two single-mode partners);
+                  and the section's second route, eq. (MScatScat2) and its
+                  partners (partial integration in t), as an independent
+                  check of the first.
 
 Pins (tests/test_oracle_*.py, all ``-m "not gpu"``) tie every function to
 something other than itself: Clifford algebra and spinor identities, the

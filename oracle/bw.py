@@ -152,6 +152,85 @@ class Vertex:
         m_sb *= np.exp(1j * (q0 - k0) * t_in)
         return np.array([m_ss, m_bs, m_sb])
 
+    # -- second route: partial integration in t -----------------------------
+    # Section "Nonlinear Breit-Wheeler": with the scattered waves split into
+    # projected, phase-removed components, integrating by parts in t turns
+    # every term into an integral over d/dt of those components; the free
+    # (H0) part of the evolution drops out mode by mode (Pi_sigma H0 = sigma E
+    # Pi_sigma on the lattice), so only the source S = -i V (psi_s + psi_b)
+    # remains and the integrand vanishes outside the field: no past term, the
+    # window [t_in, t_out] holds the whole integral.  In the reading of the
+    # first route (Lambda_+ = Pi_-, e^{-ikx} photon, alpha.eps):
+    #   ss: i e^{-i k0 t} dV/N sum_kappa sum_{s,s'} [(Pi_s S~_U)^dag G Pi_s' V~'
+    #       + (Pi_s U~)^dag G Pi_s' S~'_V] / Om_ss',  Om = s E - s' E' - k0,
+    #       V~' = FFT(V e^{ik.x}) (E' and Pi_s' at kappa - k);
+    #   bs: sum_s' i e^{i(p0-k0)t} u^dag G Pi_s'(p-k) S_V,c(p-k) / (p0 - s' E - k0);
+    #   sb: sum_s  i e^{i(q0-k0)t} (Pi_s(k-q) S_U,c(k-q))^dag G v / (s E + q0 - k0).
+    # Exact on the lattice when p, q and k are lattice momenta on the
+    # non-trivial axes (the shift theorem and the mode-wise identity hold).
+    def mdot_partial(self, t, yU, yV):
+        U, V, lat = self.U, self.V, self.U.lat
+        k3, k0, G = self.k3, self.k0, self.G
+        SU = U.rhs(t, yU) - U.kinetic(yU)
+        SV = V.rhs(t, yV) - V.kinetic(yV)
+        Uk, SUk = lat.fft(yU), lat.fft(SU)
+        Vk, SVk = lat.fft(yV * self.photon_x[None]), lat.fft(SV * self.photon_x[None])
+        kU = U.kfull
+        kV = [kU[j] - k3[j] for j in range(3)]
+        EU = np.sqrt(1.0 + sum(a ** 2 for a in kU))
+        EV = np.sqrt(1.0 + sum(a ** 2 for a in kV))
+        I4 = dirac.I4.reshape((4, 4) + (1,) * lat.dim)
+
+        def proj(kk, E, sign):
+            H = sum(dirac.ALPHA[j].reshape((4, 4) + (1,) * lat.dim) * kk[j][None, None]
+                    for j in range(3)) + dirac.BETA.reshape((4, 4) + (1,) * lat.dim)
+            return 0.5 * (I4 + sign * H / E[None, None])
+
+        acc = 0.0 + 0.0j
+        for sg in (1, -1):
+            PU, PSU = apply(proj(kU, EU, sg), Uk), apply(proj(kU, EU, sg), SUk)
+            for sgp in (1, -1):
+                PV, PSV = apply(proj(kV, EV, sgp), Vk), apply(proj(kV, EV, sgp), SVk)
+                om = sg * EU - sgp * EV - k0
+                acc += np.sum((np.conj(PSU) * apply(G, PV) + np.conj(PU) * apply(G, PSV)) / om[None])
+        m_ss = 1j * np.exp(-1j * k0 * t) * lat.dV / lat.N * acc
+
+        def cont_ft(psi, kappa):
+            ph = np.exp(-1j * sum(kappa[j] * lat.X[j] for j in range(lat.dim)))
+            return lat.dV * np.sum(psi * ph[None], axis=tuple(range(1, lat.dim + 1)))
+
+        p3, p0 = U.K, U.E
+        kap = p3 - k3
+        Ek = dirac.energy(kap)
+        Sc = cont_ft(SV, kap)
+        m_bs = sum(np.conj(U.w) @ (G @ (dirac.projector(kap, sgp) @ Sc)) / (p0 - sgp * Ek - k0) for sgp in (1, -1))
+        m_bs *= 1j * np.exp(1j * (p0 - k0) * t)
+
+        q3, q0 = -V.K, -V.E
+        kap = k3 - q3
+        Ek = dirac.energy(kap)
+        Sc = cont_ft(SU, kap)
+        m_sb = sum(np.conj(dirac.projector(kap, sg) @ Sc) @ (G @ V.w) / (sg * Ek + q0 - k0) for sg in (1, -1))
+        m_sb *= 1j * np.exp(1j * (q0 - k0) * t)
+        return np.array([m_ss, m_bs, m_sb])
+
+    def amplitude_partial(self):
+        """M by the partial-integration route: the three terms integrated over
+        [t_in, t_out] with the same augmented RK4 as the first route."""
+        win = self.U.window
+        h = -win.dt
+        yU = self.U.zero_state()
+        yV = self.V.zero_state()
+        M = np.zeros(3, dtype=complex)
+        for n in range(win.steps):
+            yU_new, sU, tt = self.U.step_stages(n, yU)
+            yV_new, sV, _ = self.V.step_stages(n, yV)
+            d = [self.mdot_partial(tt[i], sU[i], sV[i]) for i in range(4)]
+            M = M + (h / 6.0) * (d[0] + 2.0 * d[1] + 2.0 * d[2] + d[3])
+            yU, yV = yU_new, yV_new
+        terms = -M
+        return {"terms": terms, "total": complex(np.sum(terms))}
+
     def amplitude(self):
         """Returns dict with per-term finite and past parts and the total M."""
         psiU, psiV, Mt = self.run()
