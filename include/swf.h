@@ -120,6 +120,13 @@ typedef struct {
                                steps per launch), one workgroup per solve, with the state
                                held on chip; otherwise, and with 0, one launch per pass
                                and RK4 stage                                            */
+    int bw_partial;         /* 1: also integrate every BW vertex by the partial-integration
+                               route of the paper's BW section (eq. (MScatScat2) and its
+                               (back,scat), (scat,back) partners), read back with
+                               SWF_AMP_BW_PARTIAL.  Each vertex solve gets two more
+                               state-sized buffers, and every RK4 stage adds, per vertex,
+                               the source term in x space, four full forward transforms
+                               and two reductions; 0: off                              */
 } swf_options;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */
@@ -156,7 +163,13 @@ swf_status swf_sync(swf_ctx* ctx);
 enum {
     SWF_AMP_PAIR1 = 0, /* Omega(m,n), form 1 of eq. (Nmn): (U_b|V_s) + (U_s|Pi_+|V_s); i = U solve, j = V solve */
     SWF_AMP_PAIR2 = 1, /* form 2: (U_s|V_b) + (U_s|Pi_-|V_s) (= -form 1 by orthogonality)                     */
-    SWF_AMP_BW = 2     /* BW amplitude of vertex i; j = -1 total, j = 0/1/2 the (s,s)/(b,s)/(s,b) term          */
+    SWF_AMP_BW = 2,    /* BW amplitude of vertex i; j = -1 total, j = 0/1/2 the (s,s)/(b,s)/(s,b) term          */
+    SWF_AMP_BW_PARTIAL = 3 /* the same amplitude by partial integration in t (needs options.bw_partial,
+                              else SWF_E_ARG): each term is an integral over [t_in, t_out] of the
+                              energy-projected overlaps with the source -i V (psi_s + psi_b), so there
+                              is no asymptotic-past part.  Equal to SWF_AMP_BW up to the time and lattice
+                              discretisation (exactly so on the lattice when p, q and k are lattice
+                              momenta); an independent check of it                                 */
 };
 /* Amplitudes at t_in (requires steps_left == 0, else SWF_E_ORDER).
  * PAIR: coefficient of (2 pi)^(3-d) delta(p_perp + q_perp), d = dim; requires
@@ -208,7 +221,8 @@ swf_status swf_set_psi(swf_ctx* ctx, int i, const double* host, int step_index);
 
 /* Accumulated finite-time BW integrals of vertex i at the current step
  * (3 complex: (s,s), (b,s), (s,b) of int_{t_out}^{t} dt' Mdot): get / set, for
- * checkpoint and resume. */
+ * checkpoint and resume.  With options.bw_partial, i = n_vertices + v addresses
+ * vertex v's integrals of the partial-integration route. */
 swf_status swf_get_bw_state(swf_ctx* ctx, int i, double out[6]);
 swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]);
 

@@ -163,8 +163,11 @@ struct Plan {
     size_t state_bytes = 0;             // all state arrays
     // arena layout (byte offsets)
     size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_rtab = 0, off_ctab = 0,
-           off_items = 0, off_step = 0, off_M = 0, off_part = 0, off_red = 0, total = 0;
+           off_items = 0, off_step = 0, off_M = 0, off_part = 0, off_red = 0, off_M2 = 0, off_part2 = 0, total = 0;
     std::vector<size_t> solve_off;      // state offset of each solve (bytes from off_state)
+    bool bw2 = false;                   // partial-integration BW route on
+    std::vector<int> bw2_solves;        // solves of its vertices (they get the A0, A1 buffers)
+    std::vector<char> aux;              // per solve: 1 if it has the A0, A1 buffers
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -413,10 +416,22 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         const swf_vertex& V = P.verts[v];
         const swf_grid& G = P.grids[P.solves[V.u_solve].grid];
         VertexDev d;
+        memset(&d, 0, sizeof(d));
         d.su = V.u_solve;
         d.sv = V.v_solve;
         d.k0 = std::sqrt(V.k[0] * V.k[0] + V.k[1] * V.k[1] + V.k[2] * V.k[2]);
         for (int j = 0; j < 3; ++j) d.eps[j] = V.eps[j];
+        const double* pu = P.solves[V.u_solve].p;
+        const double* qv = P.solves[V.v_solve].p;
+        d.p0 = std::sqrt(1.0 + pu[0] * pu[0] + pu[1] * pu[1] + pu[2] * pu[2]);
+        d.q0 = std::sqrt(1.0 + qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2]);
+        for (int j = 0; j < 3; ++j) {
+            d.k[j] = V.k[j];
+            d.kbs[j] = pu[j] - V.k[j];
+            d.ksb[j] = V.k[j] - qv[j];
+            d.x0[j] = xcoord(G, j, 0);
+            d.dx[j] = j < G.dim ? G.L[j] / G.n[j] : 0.0;
+        }
         std::vector<cd> ph;
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < G.n[j]; ++k) ph.push_back(j < G.dim ? std::polar(1.0, V.k[j] * xcoord(G, j, k)) : cd(1.0));
@@ -445,11 +460,18 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         P.single.push_back(gr);
     }
     // ---- layout
+    P.bw2 = opt->bw_partial != 0 && n_verts > 0;
+    P.aux.assign(n_solves, 0);
+    if (P.bw2) {
+        for (const auto& V : P.verts) P.aux[V.u_solve] = P.aux[V.v_solve] = 1;
+        for (int i = 0; i < n_solves; ++i)
+            if (P.aux[i]) P.bw2_solves.push_back(i);
+    }
     size_t off = 0;
     P.off_state = 0;
     for (int i = 0; i < n_solves; ++i) {
         P.solve_off.push_back(off);
-        off += 4 * align256(4 * (size_t)P.hs[i].nsites * P.csize);
+        off += (P.aux[i] ? 6 : 4) * align256(4 * (size_t)P.hs[i].nsites * P.csize);
     }
     P.state_bytes = off;
     P.off_solves = off = align256(off);
@@ -472,6 +494,12 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     off += sizeof(double2) * 12 * (size_t)BW_BLOCKS * std::max(1, n_verts);
     P.off_red = off = align256(off);
     off += sizeof(double2) * 4 * (size_t)RED_BLOCKS;
+    if (P.bw2) {
+        P.off_M2 = off = align256(off);
+        off += sizeof(double2) * 3 * n_verts;
+        P.off_part2 = off = align256(off);
+        off += sizeof(double2) * 4 * 9 * (size_t)BW_BLOCKS * n_verts;
+    }
     P.total = align256(off);
     return SWF_OK;
 }
@@ -518,6 +546,8 @@ struct swf_ctx {
     double2* d_M() { return (double2*)(arena + P.off_M); }
     double2* d_part() { return (double2*)(arena + P.off_part); }
     double2* d_red() { return (double2*)(arena + P.off_red); }
+    double2* d_M2() { return (double2*)(arena + P.off_M2); }
+    double2* d_part2() { return (double2*)(arena + P.off_part2); }
     void* buf(int s, int role) { return arena + P.off_state + P.solve_off[s] + role * align256(4 * (size_t)P.hs[s].nsites * P.csize); }
 };
 
@@ -715,6 +745,76 @@ static int bw_accum(swf_ctx* ctx) {
     return SWF_OK;
 }
 
+// Partial-integration BW route at one RK4 stage (see bw2_src_kernel): the
+// source S of every vertex solve into its A1 buffer, the x-space Fourier sums
+// of the (b,s) and (s,b) terms, then per vertex the full transforms
+// U~ = FFT(U), S~_U = FFT(S_U), V~' = FFT(V e^{i k.x}), S~'_V = FFT(S_V e^{i k.x})
+// into A0 / A1 and the k-space (s,s) sum.  A solve's transforms are reused by
+// the next vertex that needs the same photon phase.
+static int bw2_stage(swf_ctx* ctx, int stage) {
+    const Plan& P = ctx->P;
+    const int src = stage == 0 ? swf::BUF_Y : swf::BUF_YS;
+    int r = SWF_OK;
+    for (int i : P.bw2_solves) {
+        r = row_pass(ctx, P.single[i], swf::ROW_SRC, stage, src, swf::BUF_A1, 0, 0);
+        if (r) return r;
+    }
+    swf::BwArgs b;
+    memset(&b, 0, sizeof(b));
+    b.solves = ctx->d_solves();
+    b.verts = ctx->d_verts();
+    b.step = ctx->d_step();
+    b.t_out = P.win.t_out;
+    b.dt = P.win.dt;
+    b.stage = stage;
+    b.nvert = (int)P.hv.size();
+    b.part2 = ctx->d_part2();
+    b.M2 = ctx->d_M2();
+    HIPCHK(swf::launch_bw2_src(P.fp64, b, BW_BLOCKS, ctx->st));
+    // phase held by each solve's A0/A1: NONE = A1 still holds S in x space
+    const long long NONE = -2;
+    std::vector<long long> held(P.solves.size(), NONE);
+    auto transform = [&](int i, long long ph) -> int {
+        if (held[i] == ph) return SWF_OK;
+        const Group& g = P.single[i];
+        int rr = SWF_OK;
+        if (held[i] != NONE) rr = row_pass(ctx, g, swf::ROW_SRC, stage, src, swf::BUF_A1, 0, 0);
+        const int mode = ph < 0 ? swf::ROW_FWD : swf::ROW_FWDPH;
+        const long long ph2 = ph < 0 ? 0 : ph;
+        if (!rr) rr = row_pass(ctx, g, mode, 0, src, swf::BUF_A0, 0, ph2);
+        if (!rr) rr = row_pass(ctx, g, mode, 0, swf::BUF_A1, swf::BUF_A1, 0, ph2);
+        for (int ax = 1; !rr && ax < P.grids[g.grid].dim; ++ax) {
+            rr = col_pass(ctx, g, ax, swf::COL_FWD, swf::BUF_A0);
+            if (!rr) rr = col_pass(ctx, g, ax, swf::COL_FWD, swf::BUF_A1);
+        }
+        held[i] = ph;
+        return rr;
+    };
+    for (int v = 0; v < (int)P.hv.size(); ++v) {
+        r = transform(P.hv[v].su, -1);
+        if (!r) r = transform(P.hv[v].sv, P.hv[v].phk);
+        if (r) return r;
+        b.vtx = v;
+        HIPCHK(swf::launch_bw2_kss(P.fp64, b, BW_BLOCKS, ctx->st));
+    }
+    return SWF_OK;
+}
+
+static int bw2_accum(swf_ctx* ctx) {
+    swf::BwArgs b;
+    memset(&b, 0, sizeof(b));
+    b.solves = ctx->d_solves();
+    b.verts = ctx->d_verts();
+    b.step = ctx->d_step();
+    b.t_out = ctx->P.win.t_out;
+    b.dt = ctx->P.win.dt;
+    b.nvert = (int)ctx->P.hv.size();
+    b.part2 = ctx->d_part2();
+    b.M2 = ctx->d_M2();
+    HIPCHK(swf::launch_bw2_accum(b, BW_BLOCKS, ctx->st));
+    return SWF_OK;
+}
+
 // Forward x pass Y -> T for every solve (after the state was set from the host).
 static int refresh_T(swf_ctx* ctx) {
     if (ctx->t_valid) return SWF_OK;
@@ -741,6 +841,7 @@ static int enqueue_step(swf_ctx* ctx) {
     }
     for (int s = 0; s < 4; ++s) {
         int r = bw_stage(ctx, s);
+        if (!r && ctx->P.bw2) r = bw2_stage(ctx, s);
         if (r) return r;
         for (const auto& g : groups(ctx)) {
             r = kinetic_cols(ctx, g, swf::BUF_T, true);
@@ -749,6 +850,7 @@ static int enqueue_step(swf_ctx* ctx) {
         }
     }
     int r = bw_accum(ctx);
+    if (!r && ctx->P.bw2) r = bw2_accum(ctx);
     if (r) return r;
     HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
     return SWF_OK;
@@ -1322,7 +1424,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     }
     // fill buffer pointers and upload descriptors / tables
     for (size_t i = 0; i < P.hs.size(); ++i)
-        for (int role = 0; role < 4; ++role) P.hs[i].buf[role] = ctx->buf((int)i, role);
+        for (int role = 0; role < 6; ++role) P.hs[i].buf[role] = (role < 4 || P.aux[i]) ? ctx->buf((int)i, role) : nullptr;
     INITCHK(hipMemsetAsync(ctx->arena + P.off_state, 0, P.state_bytes, ctx->st));
     INITCHK(hipMemcpyAsync(ctx->d_solves(), P.hs.data(), sizeof(SolveDev) * P.hs.size(), hipMemcpyHostToDevice, ctx->st));
     if (!P.ht.empty())
@@ -1348,6 +1450,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     INITCHK(hipMemcpyAsync(ctx->d_items(), P.items.data(), sizeof(int2) * P.items.size(), hipMemcpyHostToDevice, ctx->st));
     INITCHK(hipMemsetAsync(ctx->d_step(), 0, 256, ctx->st));
     INITCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, P.hv.size()), ctx->st));
+    if (P.bw2) INITCHK(hipMemsetAsync(ctx->d_M2(), 0, sizeof(double2) * 3 * P.hv.size(), ctx->st));
     INITCHK(hipStreamSynchronize(ctx->st));
     {
         int dev = 0, lds = 0;
@@ -1361,7 +1464,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
             for (int ax = 0; ax < 3; ++ax) {
                 const auto* k = g.k[ax];
                 if (!k) continue;
-                for (int m = 0; m < 5; ++m)
+                for (int m = 0; m < swf::ROW_NMODES; ++m)
                     INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
                 if (k->line[0] && ax == 0)
                     for (int w = 0; w < 2; ++w)
@@ -1441,6 +1544,7 @@ swf_status swf_reset(swf_ctx* ctx) {
     HIPCHK(hipMemsetAsync(ctx->arena + ctx->P.off_state, 0, ctx->P.state_bytes, ctx->st));
     HIPCHK(hipMemsetAsync(ctx->d_step(), 0, 256, ctx->st));
     HIPCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, ctx->P.hv.size()), ctx->st));
+    if (ctx->P.bw2) HIPCHK(hipMemsetAsync(ctx->d_M2(), 0, sizeof(double2) * 3 * ctx->P.hv.size(), ctx->st));
     ctx->step = 0;
     ctx->t_valid = true;
     std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
@@ -1467,6 +1571,22 @@ swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]) {
     cd val;
     if (which == SWF_AMP_PAIR1 || which == SWF_AMP_PAIR2) {
         r = pair_amp(ctx, i, j, which == SWF_AMP_PAIR1 ? 1 : 2, val);
+    } else if (which == SWF_AMP_BW_PARTIAL) {
+        if (i < 0 || i >= (int)ctx->P.hv.size() || j < -1 || j > 2) {
+            ctx->err = "bad vertex or term index";
+            return SWF_E_ARG;
+        }
+        if (!ctx->P.bw2) {
+            ctx->err = "the partial-integration route needs options.bw_partial at init";
+            return SWF_E_ARG;
+        }
+        // M2(t_in) accumulated from t_out: the terms are -M2 (no past part)
+        double2 M[3];
+        HIPCHK(hipMemcpyAsync(M, ctx->d_M2() + 3 * i, sizeof(M), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        val = 0;
+        for (int t = 0; t < 3; ++t)
+            if (j < 0 || j == t) val -= cd(M[t].x, M[t].y);
     } else if (which == SWF_AMP_BW) {
         if (i < 0 || i >= (int)ctx->P.hv.size() || j < -1 || j > 2) {
             ctx->err = "bad vertex or term index";
@@ -1650,22 +1770,31 @@ swf_status swf_set_psi(swf_ctx* ctx, int i, const double* host, int step_index) 
     return SWF_OK;
 }
 
+// Vertex i's integrals: 0 <= i < nv the first route, nv <= i < 2 nv the
+// partial-integration route (with options.bw_partial).
+static double2* bw_state_ptr(swf_ctx* ctx, int i) {
+    const int nv = (int)ctx->P.hv.size();
+    if (i >= 0 && i < nv) return ctx->d_M() + 3 * i;
+    if (ctx->P.bw2 && i >= nv && i < 2 * nv) return ctx->d_M2() + 3 * (i - nv);
+    return nullptr;
+}
+
 swf_status swf_get_bw_state(swf_ctx* ctx, int i, double out[6]) {
-    if (!ctx || !out || i < 0 || i >= (int)ctx->P.hv.size()) return SWF_E_ARG;
+    if (!ctx || !out || !bw_state_ptr(ctx, i)) return SWF_E_ARG;
     int r = enter(ctx);
     if (r) return (swf_status)r;
-    HIPCHK(hipMemcpyAsync(out, ctx->d_M() + 3 * i, 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipMemcpyAsync(out, bw_state_ptr(ctx, i), 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
     HIPCHK(hipStreamSynchronize(ctx->st));
     return SWF_OK;
 }
 
 swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]) {
-    if (!ctx || !in || i < 0 || i >= (int)ctx->P.hv.size()) return SWF_E_ARG;
+    if (!ctx || !in || !bw_state_ptr(ctx, i)) return SWF_E_ARG;
     int r = enter(ctx);
     if (r) return (swf_status)r;
-    HIPCHK(hipMemcpyAsync(ctx->d_M() + 3 * i, in, 6 * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipMemcpyAsync(bw_state_ptr(ctx, i), in, 6 * sizeof(double), hipMemcpyHostToDevice, ctx->st));
     HIPCHK(hipStreamSynchronize(ctx->st));
-    ctx->bw_done[i] = 0;
+    ctx->bw_done[i % (int)ctx->P.hv.size()] = 0;
     return SWF_OK;
 }
 

@@ -49,7 +49,8 @@ struct TermDev {
 
 // Everything a kernel needs to know about one solve.
 struct SolveDev {
-    void* buf[4];         // state arrays: Y (psi_s), ACC (RK accumulator), YS (stage input), T (FFT work)
+    void* buf[6];         // state arrays: Y (psi_s), ACC (RK accumulator), YS (stage input), T (FFT work);
+                          // A0, A1: transforms of the partial-integration BW route (NULL unless used)
     int dim;
     int n[3];
     long long nsites;     // n0 * n1 * n2
@@ -67,7 +68,7 @@ struct SolveDev {
     long long tw[3];      // offset (complex) of the twiddle table of each axis' length
 };
 
-enum { BUF_Y = 0, BUF_ACC = 1, BUF_YS = 2, BUF_T = 3 };
+enum { BUF_Y = 0, BUF_ACC = 1, BUF_YS = 2, BUF_T = 3, BUF_A0 = 4, BUF_A1 = 5 };
 
 // ---------------------------------------------------------------- FFT plans
 template <int N> struct FftPlan;

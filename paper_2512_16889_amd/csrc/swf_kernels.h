@@ -17,7 +17,9 @@
 namespace swf {
 
 // Row-pass modes.
-enum { ROW_FWD = 0, ROW_STAGE = 1, ROW_INV = 2, ROW_RHS = 3, ROW_FWDPH = 4 };
+// ROW_SRC writes the source term -i V(t) (y + psi_b(t)) of the RK4 stage
+// `stage` alone, in x space (no transform).
+enum { ROW_FWD = 0, ROW_STAGE = 1, ROW_INV = 2, ROW_RHS = 3, ROW_FWDPH = 4, ROW_SRC = 5, ROW_NMODES = 6 };
 // Column-pass modes.
 enum { COL_FWD = 0, COL_INV = 1, COL_H0 = 2 };
 
@@ -29,7 +31,7 @@ struct PassArgs {
     const int2* items;     // (solve, tile) per block
     const int* step;       // device step counter
     double t_out, dt;
-    int stage;             // RK4 stage 0..3 (ROW_STAGE)
+    int stage;             // RK4 stage 0..3 (ROW_STAGE, ROW_SRC)
     int src, dst;          // buffer roles
     int h0row;             // 1: the row pass also applies -i H0 / N (dim == 1)
     double t_explicit;     // time of ROW_RHS
@@ -215,18 +217,26 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
         store(a.dst, v);
         return;
     } else {
-        // ---- inverse transform of the k-space buffer (optionally after -i H0 / N)
-        load(BUF_T, v);
-        if (a.h0row) {
-            const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], s = (R)S->inv_n;
-            const double dk = S->dk[0];
+        if constexpr (MODE == ROW_SRC) {
+            // no kinetic term: the epilogue below adds the source to zero
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const R Kx = (R)(dk * kindex(t + T * m, N));
-                apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int m = 0; m < E; ++m) v[q][m] = cmake<C>((R)0, (R)0);
+        } else {
+            // ---- inverse transform of the k-space buffer (optionally after -i H0 / N)
+            load(BUF_T, v);
+            if (a.h0row) {
+                const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], s = (R)S->inv_n;
+                const double dk = S->dk[0];
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const R Kx = (R)(dk * kindex(t + T * m, N));
+                    apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+                }
             }
+            fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
         }
-        fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
         if constexpr (MODE == ROW_INV) {
             store(a.dst, v);
             return;
@@ -235,6 +245,9 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
             double ts;
             if constexpr (MODE == ROW_RHS) {
                 ts = a.t_explicit;
+            } else if constexpr (MODE == ROW_SRC) {
+                const double cst = a.stage == 0 ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
+                ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
             } else {
                 constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
                 ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
@@ -330,7 +343,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
             } else {
                 // state loads are independent of the barrier below: issue them first
                 C yi[4][E];
-                load(MODE == ROW_RHS ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
+                load((MODE == ROW_RHS || MODE == ROW_SRC) ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
                 __syncthreads();
                 // field A_mu on this line's points
                 R A[4][E];
@@ -367,7 +380,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
 #pragma unroll
                     for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));   // v = k
                 }
-                if constexpr (MODE == ROW_RHS) {
+                if constexpr (MODE == ROW_RHS || MODE == ROW_SRC) {
                     store(a.dst, v);
                     return;
                 } else {
@@ -711,7 +724,7 @@ struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
     int nvar;
     RowVariant row[NVAR];          // the RK4 stage pass, by variant
-    const void* row_other[5];      // other row modes (variant 0)
+    const void* row_other[ROW_NMODES];  // other row modes (variant 0)
     int row0_threads, row0_rows;
     size_t row0_lds;
     ColVariant col[NVAR];
@@ -768,6 +781,7 @@ SizeKernels make_size_kernels() {
     k.row_other[ROW_INV] = (const void*)row_kernel<R, N, 0, ROW_INV, 0>;
     k.row_other[ROW_RHS] = (const void*)row_kernel<R, N, 0, ROW_RHS, 0>;
     k.row_other[ROW_FWDPH] = (const void*)row_kernel<R, N, 0, ROW_FWDPH, 0>;
+    k.row_other[ROW_SRC] = (const void*)row_kernel<R, N, 0, ROW_SRC, 0>;
     k.row0_threads = RowVar<R, N, 0>::THREADS;
     k.row0_rows = RowVar<R, N, 0>::ROWS;
     k.row0_lds = RowVar<R, N, 0>::BYTES;

@@ -26,6 +26,12 @@ struct VertexDev {
     double k0;
     double eps[3];
     long long phk;       // complex offset of exp(i k_j x_j) tables (n0 + n1 + n2 entries)
+    // partial-integration route
+    double k[3];         // photon 3-momentum
+    double kbs[3];       // p - k: momentum of the (back, scat) term's Fourier coefficient
+    double ksb[3];       // k - q: that of the (scat, back) term
+    double p0, q0;       // electron and positron energies
+    double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
 };
 
 struct BwArgs {
@@ -38,6 +44,10 @@ struct BwArgs {
     int nvert;
     double2* part;       // [vertex][stage][block][3]
     double2* M;          // [vertex][3] accumulated integrals (device, double)
+    // partial-integration route
+    int vtx;             // vertex of a per-vertex launch
+    double2* part2;      // [vertex][stage][9][block]: k-space (s,s) sum, then 8 Fourier sums
+    double2* M2;         // [vertex][3] accumulated integrals of that route
 };
 
 // Pair-amplitude matrix contraction G[m][n] = sum_K conj(A_m[K]) B_n[K].
@@ -70,6 +80,9 @@ hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hi
 hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
 hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
+hipError_t launch_bw2_src(int fp64, const BwArgs& a, int blocks, hipStream_t st);
+hipError_t launch_bw2_kss(int fp64, const BwArgs& a, int blocks, hipStream_t st);
+hipError_t launch_bw2_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_tick(int* step, hipStream_t st);
 hipError_t launch_advance(int* step, int n, hipStream_t st);
 

@@ -282,6 +282,206 @@ __global__ void bw_accum_kernel(BwArgs a, int nblk) {
     *M = dadd(*M, dsc(s, f));
 }
 
+// ---------------------------------------------------------------------------
+// Breit-Wheeler amplitude by partial integration in t (the paper's second
+// route, eq. (MScatScat2) and its (back,scat), (scat,back) partners).  With
+// the scattered waves split into energy-projected, phase-removed parts, the
+// free evolution drops out mode by mode (Pi_sigma H0 = sigma E Pi_sigma), so
+// every term becomes a time integral over [t_in, t_out] of products with the
+// source S = -i V (psi_s + psi_b) alone.  Per RK4 stage:
+//   (s,s): i e^{-i k0 t} dV/N sum_kappa sum_{sigma,sigma'}
+//          [(Pi_sigma S~_U)^dag G Pi_sigma' V~' + (Pi_sigma U~)^dag G Pi_sigma' S~'_V] / Om,
+//          Om = sigma E(kappa) - sigma' E(kappa - k) - k0, V~' = FFT(V e^{i k.x});
+//   (b,s): i e^{i(p0-k0)t} sum_sigma' u^dag G Pi_sigma'(p-k) S_V,c(p-k) / (p0 - sigma' E(p-k) - k0);
+//   (s,b): i e^{i(q0-k0)t} sum_sigma (Pi_sigma(k-q) S_U,c(k-q))^dag G v / (sigma E(k-q) + q0 - k0);
+// G = alpha.eps, F_c(kappa) = dV sum_x F(x) e^{-i kappa.x}.  The transforms
+// live in the A0 (state) and A1 (source) buffers of each vertex solve.
+
+// x-space part: the 8 Fourier sums of S_V at p - k and S_U at k - q for every
+// vertex (blockIdx.y), read from the A1 buffers while they hold S in x space.
+template <class R>
+__global__ void __launch_bounds__(RED_THREADS) bw2_src_kernel(BwArgs a) {
+    using C = cpx<R>;
+    const VertexDev* V = a.verts + blockIdx.y;
+    const SolveDev* SU = a.solves + V->su;
+    const SolveDev* SV = a.solves + V->sv;
+    const C* SrcU = reinterpret_cast<const C*>(SU->buf[BUF_A1]);
+    const C* SrcV = reinterpret_cast<const C*>(SV->buf[BUF_A1]);
+    const long long ns = SU->nsites;
+    double2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = d2(0, 0);
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
+        int x, y, z;
+        site_xyz(i, SU, x, y, z);
+        const double X[3] = {V->x0[0] + x * V->dx[0], V->x0[1] + y * V->dx[1], V->x0[2] + z * V->dx[2]};
+        double pb = 0.0, ps = 0.0;
+        for (int j = 0; j < SU->dim; ++j) {
+            pb += V->kbs[j] * X[j];
+            ps += V->ksb[j] * X[j];
+        }
+        double sn, cs;
+        sincos(-pb, &sn, &cs);
+        const double2 eb = d2(cs, sn);
+        sincos(-ps, &sn, &cs);
+        const double2 es = d2(cs, sn);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[q] = dadd(acc[q], dmul(todbl(SrcV[q * ns + i]), eb));
+            acc[4 + q] = dadd(acc[4 + q], dmul(todbl(SrcU[q * ns + i]), es));
+        }
+    }
+    double2* out = a.part2 + ((long long)blockIdx.y * 4 + a.stage) * 9 * (long long)gridDim.x + gridDim.x;
+    block_sum_store<8>(acc, out);
+}
+
+// k-space (s,s) sum of vertex a.vtx (without the factor i e^{-i k0 t} dV/N).
+template <class R>
+__global__ void __launch_bounds__(RED_THREADS) bw2_kss_kernel(BwArgs a) {
+    using C = cpx<R>;
+    const VertexDev* V = a.verts + a.vtx;
+    const SolveDev* SU = a.solves + V->su;
+    const SolveDev* SV = a.solves + V->sv;
+    const C* Uk = reinterpret_cast<const C*>(SU->buf[BUF_A0]);
+    const C* SUk = reinterpret_cast<const C*>(SU->buf[BUF_A1]);
+    const C* Vk = reinterpret_cast<const C*>(SV->buf[BUF_A0]);
+    const C* SVk = reinterpret_cast<const C*>(SV->buf[BUF_A1]);
+    const long long ns = SU->nsites;
+    double2 acc[1] = {d2(0, 0)};
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
+        int x, y, z;
+        site_xyz(i, SU, x, y, z);
+        double Kx, Ky, Kz;
+        site_k(SU, x, y, z, Kx, Ky, Kz);
+        const double Qx = Kx - V->k[0], Qy = Ky - V->k[1], Qz = Kz - V->k[2];
+        const double E = sqrt(1.0 + Kx * Kx + Ky * Ky + Kz * Kz);
+        const double Ep = sqrt(1.0 + Qx * Qx + Qy * Qy + Qz * Qz);
+        double2 u[4], su[4], v[4], sv[4], hu[4], hsu[4], hv[4], hsv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u[q] = todbl(Uk[q * ns + i]);
+            su[q] = todbl(SUk[q * ns + i]);
+            v[q] = todbl(Vk[q * ns + i]);
+            sv[q] = todbl(SVk[q * ns + i]);
+        }
+        h0d(u, hu, Kx, Ky, Kz);
+        h0d(su, hsu, Kx, Ky, Kz);
+        h0d(v, hv, Qx, Qy, Qz);
+        h0d(sv, hsv, Qx, Qy, Qz);
+        for (int sg = -1; sg <= 1; sg += 2) {
+            double2 PU[4], PSU[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                PU[q] = dsc(dadd(u[q], dsc(hu[q], sg / E)), 0.5);
+                PSU[q] = dsc(dadd(su[q], dsc(hsu[q], sg / E)), 0.5);
+            }
+            for (int sp = -1; sp <= 1; sp += 2) {
+                double2 PV[4], PSV[4], GV[4], GSV[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    PV[q] = dsc(dadd(v[q], dsc(hv[q], sp / Ep)), 0.5);
+                    PSV[q] = dsc(dadd(sv[q], dsc(hsv[q], sp / Ep)), 0.5);
+                }
+                gam_eps(PV, GV, V->eps);
+                gam_eps(PSV, GSV, V->eps);
+                double2 s = d2(0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s = dadd(s, dadd(dcmul(PSU[q], GV[q]), dcmul(PU[q], GSV[q])));
+                const double w = sg * E - sp * Ep - V->k0;
+                acc[0] = dadd(acc[0], dsc(s, 1.0 / w));
+            }
+        }
+    }
+    double2* out = a.part2 + ((long long)a.vtx * 4 + a.stage) * 9 * (long long)gridDim.x;
+    block_sum_store<1>(acc, out);
+}
+
+// Pi_sigma(K) f = (f + sigma H0(K) f / E(K)) / 2 at a (possibly off-lattice) K.
+__device__ void proj_at(const double2 (&f)[4], double2 (&o)[4], const double* K, int sigma) {
+    double2 h[4];
+    h0d(f, h, K[0], K[1], K[2]);
+    const double E = sqrt(1.0 + K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = dsc(dadd(f[q], dsc(h[q], sigma / E)), 0.5);
+}
+
+// M2_ab += (h/6) (d0 + 2 d1 + 2 d2 + d3) from the stage sums, in a fixed order;
+// one thread per (vertex, term).
+__global__ void bw2_accum_kernel(BwArgs a, int nblk) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.nvert * 3) return;
+    const int v = gid / 3, term = gid % 3;
+    const VertexDev* V = a.verts + v;
+    const SolveDev* SU = a.solves + V->su;
+    const SolveDev* SV = a.solves + V->sv;
+    const double wst[4] = {1.0, 2.0, 2.0, 1.0};
+    const int n = *a.step;
+    double2 s = d2(0, 0);
+    for (int st = 0; st < 4; ++st) {
+        const double cst = st == 0 ? 0.0 : (st == 3 ? 1.0 : 0.5);
+        const double t = a.t_out - (double)n * a.dt - cst * a.dt;
+        const double2* p = a.part2 + ((long long)v * 4 + st) * 9 * (long long)nblk;
+        double2 d;
+        if (term == 0) {
+            double2 ss = d2(0, 0);
+            for (int b = 0; b < nblk; ++b) ss = dadd(ss, p[b]);
+            double sn, cs;
+            sincos(-V->k0 * t, &sn, &cs);
+            // i e^{-i k0 t} dV/N
+            d = dsc(dmul(d2(-sn, cs), ss), SU->dV * SU->inv_n);
+        } else {
+            // F_c = dV sum over blocks of the x-space sums
+            const int o = term == 1 ? 0 : 4;
+            double2 F[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double2 f = d2(0, 0);
+                for (int b = 0; b < nblk; ++b) f = dadd(f, p[nblk + (long long)b * 8 + o + q]);
+                F[q] = dsc(f, SU->dV);
+            }
+            double2 m = d2(0, 0);
+            if (term == 1) {
+                double2 u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = d2(SU->w[2 * q], SU->w[2 * q + 1]);
+                const double Ek = sqrt(1.0 + V->kbs[0] * V->kbs[0] + V->kbs[1] * V->kbs[1] + V->kbs[2] * V->kbs[2]);
+                for (int sp = -1; sp <= 1; sp += 2) {
+                    double2 PF[4], GF[4];
+                    proj_at(F, PF, V->kbs, sp);
+                    gam_eps(PF, GF, V->eps);
+                    double2 dot = d2(0, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dot = dadd(dot, dcmul(u[q], GF[q]));
+                    m = dadd(m, dsc(dot, 1.0 / (V->p0 - sp * Ek - V->k0)));
+                }
+                double sn, cs;
+                sincos((V->p0 - V->k0) * t, &sn, &cs);
+                d = dmul(d2(-sn, cs), m);   // i e^{i(p0-k0)t} m
+            } else {
+                double2 vs[4], gv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vs[q] = d2(SV->w[2 * q], SV->w[2 * q + 1]);
+                gam_eps(vs, gv, V->eps);
+                const double Ek = sqrt(1.0 + V->ksb[0] * V->ksb[0] + V->ksb[1] * V->ksb[1] + V->ksb[2] * V->ksb[2]);
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    double2 PF[4];
+                    proj_at(F, PF, V->ksb, sg);
+                    double2 dot = d2(0, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dot = dadd(dot, dcmul(PF[q], gv[q]));
+                    m = dadd(m, dsc(dot, 1.0 / (sg * Ek + V->q0 - V->k0)));
+                }
+                double sn, cs;
+                sincos((V->q0 - V->k0) * t, &sn, &cs);
+                d = dmul(d2(-sn, cs), m);   // i e^{i(q0-k0)t} m
+            }
+        }
+        s = dadd(s, dsc(d, wst[st]));
+    }
+    double2* M = a.M2 + (long long)v * 3 + term;
+    *M = dadd(*M, dsc(s, -a.dt / 6.0));
+}
+
 __global__ void tick_kernel(int* step, int n) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(step, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -315,6 +515,27 @@ hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st) {
     const int threads = 64;
     const int blocks = (a.nvert * 3 + threads - 1) / threads;
     hipLaunchKernelGGL(bw_accum_kernel, dim3(blocks), dim3(threads), 0, st, a, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw2_src(int fp64, const BwArgs& a, int blocks, hipStream_t st) {
+    const dim3 g(blocks, a.nvert), b(RED_THREADS);
+    if (fp64) hipLaunchKernelGGL(bw2_src_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(bw2_src_kernel<float>, g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw2_kss(int fp64, const BwArgs& a, int blocks, hipStream_t st) {
+    const dim3 g(blocks), b(RED_THREADS);
+    if (fp64) hipLaunchKernelGGL(bw2_kss_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(bw2_kss_kernel<float>, g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw2_accum(const BwArgs& a, int nblk, hipStream_t st) {
+    const int threads = 64;
+    const int blocks = (a.nvert * 3 + threads - 1) / threads;
+    hipLaunchKernelGGL(bw2_accum_kernel, dim3(blocks), dim3(threads), 0, st, a, nblk);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 SWF_OK, SWF_E_ARG, SWF_E_NOMEM, SWF_E_HIP, SWF_E_ORDER, SWF_E_UNSUPPORTED, SWF_E_NONFINITE = range(7)
 SWF_FP64, SWF_MIXED = 0, 1
-AMP_PAIR1, AMP_PAIR2, AMP_BW = 0, 1, 2
+AMP_PAIR1, AMP_PAIR2, AMP_BW, AMP_BW_PARTIAL = 0, 1, 2, 3
 P_MARGINAL_E, P_MARGINAL_POS, P_PAIR, P_BW = 0, 1, 2, 3
 STAT_ROW, STAT_COLY, STAT_COLZ, STAT_BW, STAT_OTHER = range(5)
 
@@ -64,7 +64,7 @@ class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int), ("batched", C.c_int),
                 ("profile", C.c_int), ("tune", C.c_int), ("tune_cache", C.c_char_p), ("chunk", C.c_int),
-                ("force_variant", C.c_int), ("persistent", C.c_int)]
+                ("force_variant", C.c_int), ("persistent", C.c_int), ("bw_partial", C.c_int)]
 
 
 _P = C.POINTER
@@ -163,7 +163,7 @@ class Context:
     def __init__(self, problem, precision: str = "fp64", use_graph: bool = False, batched: bool = True,
                  profile: bool = False, device_workspace: bool = True, tune: bool = False,
                  tune_cache: str | None = None, chunk: int = 0, variant: int | None = None,
-                 persistent: bool = True):
+                 persistent: bool = True, bw_partial: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("the SWF solver runs on the GPU only; no device is visible")
         self.problem = problem
@@ -178,6 +178,7 @@ class Context:
         self.opt.chunk = int(chunk)
         self.opt.force_variant = 0 if variant is None else int(variant) + 1
         self.opt.persistent = int(persistent)
+        self.opt.bw_partial = int(bw_partial)
         self._tune_cache = tune_cache.encode() if tune_cache else None
         self.opt.tune_cache = self._tune_cache
         self.opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -260,6 +261,9 @@ class Context:
 
     def bw(self, v: int, term: int = -1) -> complex:
         return self.amplitude(AMP_BW, v, term)
+
+    def bw_partial(self, v: int, term: int = -1) -> complex:
+        return self.amplitude(AMP_BW_PARTIAL, v, term)
 
     def diagnostics(self, i: int):
         out = (C.c_double * 4)()

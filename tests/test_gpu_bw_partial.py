@@ -1,0 +1,192 @@
+"""GPU parity of the Breit-Wheeler amplitude by partial integration in t
+(options.bw_partial, SWF_AMP_BW_PARTIAL), through the C ABI.
+
+The second route of the paper's BW section integrates, per term, the
+energy-projected overlaps with the source -i V (psi_s + psi_b) over the
+window; it has no past part.  Checked against
+* the oracle's Vertex.amplitude_partial, term by term, in 1D (Fig. 7
+  kinematics, two spin pairs), 2D (off-lattice momenta, trivial-axis
+  momentum) and 3D, FP64 to 1e-9 of each term's size;
+* the first route on the GPU (finite + past): equal to the discretisation
+  error where p, q, k are lattice momenta, and the exact spin ratio of
+  eq. (MparaE);
+* two vertices that share a V solve with different photons (the V
+  transforms are redone for the second photon);
+* graph replay (bitwise equal to eager launches), checkpoint and resume of
+  the route's integrals, mixed precision, and the error paths.
+"""
+import numpy as np
+import pytest
+
+import swf_workloads as W
+from oracle import bw as obw
+
+from swf_cases import field_mix, grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2512_16889_amd import swf
+    return swf
+
+
+def term_close(got, want, tol):
+    got, want = np.asarray(got), np.asarray(want)
+    assert np.all(np.abs(want) > 0)
+    err = np.abs(got - want) / np.abs(want)
+    assert np.all(err < tol), (err, got, want)
+
+
+def fig7(dt=0.1, spins=((1, 1), (1, -1))):
+    P = 2 * np.pi * 4 / 160.0
+    return W.config_bw_1d(P=P, n=128, L=160.0, dt=dt, t_half=25.0, spins=spins)
+
+
+def bw2d():
+    g = grid(2, (32, 32), (40.0, 40.0))
+    F = [W.Term(1, 0.8, W.gauss(2.0, k=0.5), [W.gauss(5.0), W.gauss(6.0), W.const()]),
+         W.Term(0, 0.2, W.sech2(2.0), [W.ugauss(4.0), W.gauss(5.0), W.const()])]
+    k = [2 * np.pi * 2 / 40.0, 0.0, 1.1]
+    p = [2 * np.pi * 3 / 40.0 + 0.05, -2 * np.pi / 40.0, 0.4]
+    q = [0.2, 0.3, 0.7]
+    return W.Problem("bw2", [g], [F], [W.Solve(0, 1, p), W.Solve(1, -1, q)], W.Window(-6.0, 6.0, 0.05),
+                     [W.Vertex(0, 1, k, [0.0, 0.6, 0.8])])
+
+
+def shared_v_2d():
+    # U0, U1 and one V; the vertices use different photons (k_z = p_z + q_z each)
+    g = grid(2, (32, 32), (36.0, 36.0))
+    q = [0.1, -0.2, 0.3]
+    p0 = [0.3, 0.1, 0.5]
+    p1 = [-0.2, 0.25, -0.1]
+    k0 = [2 * np.pi * 2 / 36.0, -2 * np.pi / 36.0, p0[2] + q[2]]
+    k1 = [0.4, 0.7, p1[2] + q[2]]
+    return W.Problem("bw2s", [g], [field_mix(2)],
+                     [W.Solve(0, 1, p0), W.Solve(1, -1, q), W.Solve(0, -1, p1)], W.Window(-2.0, 2.0, 0.05),
+                     [W.Vertex(0, 1, k0, [1.0, 0.0, 0.0]), W.Vertex(2, 1, k1, [0.0, 0.6, 0.8])])
+
+
+def bw3d():
+    g = grid(3, (16, 16, 16), (18.0, 18.0, 18.0))
+    p = [2 * np.pi * 2 / 18.0, 0.0, 2 * np.pi / 18.0]
+    q = [-2 * np.pi / 18.0, 2 * np.pi / 18.0, 0.0]
+    k = [2 * np.pi * 1 / 18.0, 2 * np.pi / 18.0, 2 * np.pi * 2 / 18.0]
+    return W.Problem("bw3", [g], [field_mix(3)], [W.Solve(0, 1, p), W.Solve(1, 1, q)], W.Window(-1.5, 1.5, 0.05),
+                     [W.Vertex(0, 1, k, [0.0, 1.0, 0.0])])
+
+
+def test_partial_route_1d_fig7_vs_oracle(S):
+    prob = fig7()
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        for v in range(len(prob.vertices)):
+            ref = obw.Vertex(prob, v).amplitude_partial()
+            got = [ctx.bw_partial(v, t) for t in range(3)]
+            assert np.all(np.abs(ref["terms"]) > 1.0)
+            term_close(got, ref["terms"], 1e-9)
+            assert abs(ctx.bw_partial(v) - ref["total"]) <= 1e-9 * np.abs(ref["terms"]).max()
+            # the first route, also on the GPU: lattice momenta, so the two differ by
+            # the time discretisation only (order 4 in dt; the oracle pins 3e-6 at dt = 0.1)
+            term_close(got, [ctx.bw(v, t) for t in range(3)], 3e-6)
+        # eq. (MparaE): M(+,-) / M(+,+) = -i p2 holds by this route as well
+        assert ctx.bw_partial(1) / ctx.bw_partial(0) == pytest.approx(-0.6j, abs=1e-7)
+
+
+@pytest.mark.parametrize("make", [bw2d, bw3d], ids=["2d", "3d"])
+def test_partial_route_vs_oracle(S, make):
+    prob = make()
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        ref = obw.Vertex(prob, 0).amplitude_partial()
+        got = [ctx.bw_partial(0, t) for t in range(3)]
+        term_close(got, ref["terms"], 1e-9)
+
+
+def test_partial_route_shared_v_two_photons(S):
+    prob = shared_v_2d()
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        for v in range(2):
+            ref = obw.Vertex(prob, v).amplitude_partial()
+            term_close([ctx.bw_partial(v, t) for t in range(3)], ref["terms"], 1e-9)
+
+
+def test_partial_route_first_route_unchanged(S):
+    # turning the second route on leaves the first route's integrals bitwise alone
+    prob = bw2d()
+    with S.Context(prob, precision="fp64") as ctx:
+        ctx.step()
+        plain = [ctx.bw(0, t) for t in range(3)]
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        assert [ctx.bw(0, t) for t in range(3)] == plain
+
+
+def test_partial_route_graph_replay_and_reset(S):
+    prob = shared_v_2d()
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        eager = [ctx.bw_partial(v, t) for v in range(2) for t in range(3)]
+    with S.Context(prob, precision="fp64", bw_partial=True, use_graph=True) as ctx:
+        for _ in range(2):                          # the second pass replays after a reset
+            ctx.step(7)
+            ctx.sync()
+            ctx.step()
+            assert [ctx.bw_partial(v, t) for v in range(2) for t in range(3)] == eager
+            ctx.reset()
+
+
+def test_partial_route_checkpoint_resume(S):
+    prob = bw2d()
+    total = prob.window.steps
+    half = total // 2
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step()
+        want = [ctx.bw_partial(0, t) for t in range(3)]
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        ctx.step(half)
+        psi = [ctx.get_psi(i) for i in range(2)]
+        m1, m2 = ctx.get_bw_state(0), ctx.get_bw_state(1)
+    assert np.any(m2 != 0)
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        for i in range(2):
+            ctx.set_psi(i, psi[i], half)
+        ctx.set_bw_state(0, m1)
+        ctx.set_bw_state(1, m2)
+        ctx.step()
+        term_close([ctx.bw_partial(0, t) for t in range(3)], want, 1e-12)
+
+
+def test_partial_route_mixed(S):
+    # FP32 states and transforms, FP64 sums: each term against the FP64 oracle
+    prob = fig7(spins=((1, 1),))
+    with S.Context(prob, precision="mixed", bw_partial=True) as ctx:
+        ctx.step()
+        ref = obw.Vertex(prob, 0).amplitude_partial()
+        term_close([ctx.bw_partial(0, t) for t in range(3)], ref["terms"], 1e-4)
+
+
+def test_partial_route_errors(S):
+    prob = bw2d()
+    with S.Context(prob, precision="fp64") as ctx:
+        ctx.step()
+        with pytest.raises(S.SwfError) as e:
+            ctx.bw_partial(0)
+        assert e.value.code == S.SWF_E_ARG
+        with pytest.raises(S.SwfError) as e:
+            ctx.get_bw_state(1)                     # no second bank without the option
+        assert e.value.code == S.SWF_E_ARG
+    with S.Context(prob, precision="fp64", bw_partial=True) as ctx:
+        with pytest.raises(S.SwfError) as e:
+            ctx.bw_partial(0)                       # before t_in
+        assert e.value.code == S.SWF_E_ORDER
+        ctx.step()
+        for v, t in ((1, 0), (0, 3), (-1, 0)):
+            with pytest.raises(S.SwfError) as e:
+                ctx.bw_partial(v, t)
+            assert e.value.code == S.SWF_E_ARG
+        with pytest.raises(S.SwfError) as e:
+            ctx.get_bw_state(2)
+        assert e.value.code == S.SWF_E_ARG
