@@ -85,7 +85,7 @@ def stored_traffic(precision, n, variant):
     return sum(per_stage) / 4
 
 
-def run_job(ctx, prob, progress=0):
+def run_job(ctx, prob, progress=0, bw_partial=False):
     if progress > 0:
         # chunks of `progress` steps, each synchronised and reported (long jobs)
         left = prob.window.steps
@@ -100,30 +100,38 @@ def run_job(ctx, prob, progress=0):
         out.append(ctx.marginal(i))
     for v in range(len(prob.vertices)):
         out.append(abs(ctx.bw(v)) ** 2)
+    if bw_partial:
+        # |M|^2 by the partial-integration route, kept apart from the P check
+        ctx.last_bw_partial = [abs(ctx.bw_partial(v)) ** 2 for v in range(len(prob.vertices))]
     return out
 
 
 def timed_jobs(S, torch, prob, precision, K, W, batched=True, graph=False, profile=True, tune=True, chunk=0,
-               variant=None, progress=0):
+               variant=None, progress=0, bw_partial=False):
     ctx = S.Context(prob, precision=precision, batched=batched, use_graph=graph, profile=profile, tune=tune,
-                    chunk=chunk, variant=variant)
+                    chunk=chunk, variant=variant, bw_partial=bw_partial)
     report = ctx.tune_report()
     results = None
     for _ in range(W):
         ctx.reset()
-        run_job(ctx, prob, progress)
+        run_job(ctx, prob, progress, bw_partial)
     ctx.sync()
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
         ctx.reset()
-        results = run_job(ctx, prob, progress)
+        results = run_job(ctx, prob, progress, bw_partial)
     ctx.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stats = {k: ctx.kernel_stats(k) for k in range(6)} if profile else {}
     norms = [ctx.diagnostics(i)[0] for i in range(len(prob.solves))]
+    if bw_partial:
+        nb = len(prob.vertices)
+        m1 = results[len(results) - nb:]
+        m2 = ctx.last_bw_partial
+        stats["bw_routes_max_rel_diff"] = max(abs(a - b) / abs(b) for a, b in zip(m2, m1) if b != 0)
     ctx.close()
     return wall, results, stats, report, norms
 
@@ -182,6 +190,8 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="force tile variant 0..3 for every pass")
     ap.add_argument("--progress", type=int, default=0, metavar="STEPS",
                     help="step in synchronised chunks of STEPS and report each (long jobs)")
+    ap.add_argument("--bw-partial", action="store_true",
+                    help="also integrate the BW vertices by the partial-integration route (timed with the job)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -215,6 +225,7 @@ def main():
              5: "1D whole-loop kernel (all steps on chip)"}
 
     def summarize(wall, stats):
+        routes = stats.pop("bw_routes_max_rel_diff", None)
         dom = max((k for k in stats if k != 4), key=lambda k: stats[k][1])
         n_l, ms, by = stats[dom]
         achieved = by / (ms * 1e-3) / 1e9
@@ -224,13 +235,19 @@ def main():
         roof = {"bound": "hbm", "kernel": names.get(dom, str(dom)), "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": ms / max(n_l, 1),
                 "algorithmic_bytes_per_launch": by / max(n_l, 1)}
-        return {"value": su * args.steps / wall, "ms_per_step": wall / args.steps * 1e3, "roofline": roof,
-                "kernels": kern}
+        res = {"value": su * args.steps / wall, "ms_per_step": wall / args.steps * 1e3, "roofline": roof,
+               "kernels": kern}
+        if routes is not None:
+            res["bw_partial_route"] = {"timed_with_job": True, "max_rel_diff_of_M2_vs_first_route": routes}
+        return res
 
     paths = {}
+    if args.bw_partial and not prob.vertices:
+        raise SystemExit("--bw-partial needs a workload with BW vertices (bw3d)")
     wall, P_mixed, stats, tune_rep, norms_m = timed_jobs(S, torch, prob, "mixed", args.steps, args.warmup,
                                                         chunk=args.chunk, tune=not args.no_tune,
-                                                        variant=args.variant, progress=args.progress)
+                                                        variant=args.variant, progress=args.progress,
+                                                        bw_partial=args.bw_partial)
     paths["mixed_batched"] = summarize(wall, stats)
     paths["mixed_batched"]["autotune"] = tune_rep
     print(f"[bench] mixed batched: {wall:.2f} s for {args.steps} job(s) -> {paths['mixed_batched']['value']:.4e} "
@@ -239,7 +256,8 @@ def main():
     if not args.no_fp64:
         wall64, P64, stats64, tune64, norms64 = timed_jobs(S, torch, prob, "fp64", args.steps, args.warmup,
                                                            chunk=args.chunk, tune=not args.no_tune,
-                                                           variant=args.variant, progress=args.progress)
+                                                           variant=args.variant, progress=args.progress,
+                                                           bw_partial=args.bw_partial)
         paths["fp64_batched"] = summarize(wall64, stats64)
         paths["fp64_batched"]["autotune"] = tune64
         rel = [abs(a - b) / abs(b) for a, b in zip(P_mixed, P64) if b != 0]
@@ -273,7 +291,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "solves": len(prob.solves), "grid": prob.grids[0].n[:prob.grids[0].dim],
                    "rk4_steps": steps, "timed_path": headline, "p_tolerance": P_TOL,
-                   "parallelism": "single GPU, batched solves", "chunk": args.chunk},
+                   "parallelism": "single GPU, batched solves", "chunk": args.chunk,
+                   "bw_partial": bool(args.bw_partial)},
         "roofline": H["roofline"],
         "kernels": H["kernels"],
         "paths": paths,
