@@ -221,7 +221,7 @@ def main():
           file=sys.stderr, flush=True)
 
     names = {0: "row pass (x FFTs + RK4 stage epilogue)", 1: "column pass y (stepping)",
-             2: "column pass z (stepping)", 3: "BW vertex reduction", 4: "t_in transforms",
+             2: "column pass z (stepping)", 3: "BW vertex reduction", 4: "other passes (t_in transforms, BW partial-integration route)",
              5: "1D whole-loop kernel (all steps on chip)"}
 
     def summarize(wall, stats):
