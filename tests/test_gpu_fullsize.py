@@ -13,7 +13,9 @@
   320^3) are too large for the oracle; there a pure-gauge field is stepped
   through the same kernels and tiles and the scattered wave is compared at
   sampled sites with its closed form (exp(-i Lambda) - 1) psi_back, which
-  holds at any grid size.
+  holds at any grid size.  At 320^3 the BW vertex integrals are checked the
+  same way: with that closed form every integrand is a plane-wave factor
+  times lattice sums that reduce to one-dimensional sums.
 FP64 to 1e-12 (one step) or 1e-5 (closed form, limited by the RK4 and
 spectral discretisation); mixed precision to 2e-6 (one step) or 3e-4
 (closed form).
@@ -140,6 +142,76 @@ def test_launch_config_3d_320_pure_gauge(S):
     prob.vertices = []
     prob.window = W.Window(0.0, 12.0, 0.025)
     pure_gauge_check(S, prob, lam0, tau, w, "mixed", prob.window.steps)
+
+
+def pure_gauge_bw_reference(prob, lam0, tau, w, nsteps):
+    """Accumulated vertex integrals M_ab after nsteps for a pure-gauge field,
+    where every scattered wave is (exp(-i Lambda) - 1) psi_back.  The three
+    integrands are then plane-wave factors times lattice sums of
+    2 - 2 cos Lambda, exp(-i Lambda) - 1 and exp(i Lambda) - 1 with
+    Lambda = c(t) g(x) g(y) g(z); their power series in c reduce every sum to
+    products of one-dimensional sums (exact to rounding at any grid size).
+    Integrated with the RK4 weights at the stage times (Simpson), which agrees
+    with the augmented RK4 to O(dt^4)."""
+    from math import factorial
+    from oracle import dirac
+    from oracle.bw import gamma_eps
+    g = prob.grids[0]
+    win = prob.window
+    x = [-g.L[j] / 2 + np.arange(g.n[j]) * g.L[j] / g.n[j] for j in range(3)]
+    dV = np.prod([g.L[j] / g.n[j] for j in range(3)])
+    J = 48
+    out = []
+    for vx in prob.vertices:
+        wu, Eu, Ku = dirac.background_spinor(0, prob.solves[vx.u_solve].spin, prob.solves[vx.u_solve].p)
+        wv, Ev, Kv = dirac.background_spinor(1, prob.solves[vx.v_solve].spin, prob.solves[vx.v_solve].p)
+        k3 = np.asarray(vx.k, dtype=float)
+        k0 = float(np.linalg.norm(k3))
+        amp = np.conj(wu) @ (gamma_eps(vx.eps) @ wv)
+        Q = Kv - Ku + k3
+        # S_j = prod over axes of sum_i g(x_i)^j e^{i Q_a x_i}
+        Sj = np.array([np.prod([np.sum(np.exp(-j * x[a] ** 2 / w ** 2 + 1j * Q[a] * x[a])) for a in range(3)])
+                       for j in range(J + 1)])
+
+        def mdot(t):
+            c = lam0 * np.exp(-t ** 2 / tau ** 2)
+            s_e = sum((-1j * c) ** j * Sj[j] / factorial(j) for j in range(1, J + 1))        # exp(-i L) - 1
+            s_ec = sum((1j * c) ** j * Sj[j] / factorial(j) for j in range(1, J + 1))        # exp(+i L) - 1
+            s_cos = -(s_e + s_ec)                                                              # 2 - 2 cos L
+            ph = dV * amp * np.exp(1j * (Eu - Ev - k0) * t)
+            return ph * np.array([s_cos, s_e, s_ec])
+
+        h = -win.dt
+        M = np.zeros(3, dtype=complex)
+        for n in range(nsteps):
+            t = win.t_out - n * win.dt
+            M += h / 6.0 * (mdot(t) + 4.0 * mdot(t + h / 2) + mdot(t + h))
+        out.append(M)
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-5), ("mixed", 3e-4)])
+def test_launch_config_bw_320_pure_gauge(S, prec, tol):
+    # the BW vertex reduction in the 320^3 launch configuration (one momentum,
+    # four spin pairs: 2 U + 2 V solves, 4 vertices) against the closed form;
+    # each vertex gets its own photon so that every vertex has its own value
+    lam0, tau, w = 0.8, 2.0, 8.0
+    prob = W.config_bw_3d(n_p=1)
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 3)]
+    photons = [([0.0, 0.0, 2.0], [-1.0, 0.0, 0.0]), ([0.3, 0.0, 1.9], [0.0, 1.0, 0.0]),
+               ([0.0, -0.4, 1.8], [0.6, 0.0, 0.8]), ([0.2, 0.25, 2.2], [0.0, 0.8, -0.6])]
+    prob.vertices = [W.Vertex(vx.u_solve, vx.v_solve, k, e) for vx, (k, e) in zip(prob.vertices, photons)]
+    prob.window = W.Window(0.0, 8.0, 0.05)             # Lambda(t_out) ~ 1e-7, ends at the pulse maximum
+    nsteps = prob.window.steps
+    ref = pure_gauge_bw_reference(prob, lam0, tau, w, nsteps)
+    with S.Context(prob, precision=prec) as ctx:
+        ctx.step(nsteps)
+        ctx.sync()
+        for v in range(len(prob.vertices)):
+            got = ctx.get_bw_state(v)
+            assert np.abs(ref[v]).min() > 1.0
+            err = float(np.abs(got - ref[v]).max() / np.abs(ref[v]).max())
+            assert err < tol, (prec, v, err, got, ref[v])
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
