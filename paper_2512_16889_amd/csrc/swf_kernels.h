@@ -140,6 +140,21 @@ template <class C> __device__ __forceinline__ void gstore(gptr<nv2<decltype(C::x
     v.y = c.y;
     p[i] = v;
 }
+// streaming (non-temporal) load and store for the row pass: it reads and
+// writes each line once per launch, and nothing touches the line again before
+// the whole batch has been swept, so caching it only evicts other data.  (The
+// column pass keeps ordinary accesses: tiles that share 128-byte lines meet
+// in L2.)
+template <class C> __device__ __forceinline__ C gload_nt(gptr<const nv2<decltype(C::x)>> p, long long i) {
+    const nv2<decltype(C::x)> v = __builtin_nontemporal_load(&p[i]);
+    return cmake<C>(v.x, v.y);
+}
+template <class C> __device__ __forceinline__ void gstore_nt(gptr<nv2<decltype(C::x)>> p, long long i, C c) {
+    nv2<decltype(C::x)> v;
+    v.x = c.x;
+    v.y = c.y;
+    __builtin_nontemporal_store(v, &p[i]);
+}
 template <class R> __device__ __forceinline__ gptr<const nv2<R>> cview(const void* p) {
     return (gptr<const nv2<R>>)(reinterpret_cast<const nv2<R>*>(p));
 }
@@ -189,7 +204,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) w[q][m] = gload<C>(p, q * ns + T * m);
+            for (int m = 0; m < E; ++m) w[q][m] = gload_nt<C>(p, q * ns + T * m);
     };
     auto store = [&](int role, const C (&w)[4][E]) {
         if (!act) return;
@@ -197,7 +212,7 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int m = 0; m < E; ++m) gstore<C>(p, q * ns + T * m, w[q][m]);
+            for (int m = 0; m < E; ++m) gstore_nt<C>(p, q * ns + T * m, w[q][m]);
     };
 
     C v[4][E];
