@@ -9,6 +9,8 @@ against what holds exactly.
   coupling, on the pass path, against the oracle.
 * A window of a single RK4 step.
 * The smallest FFT length on every axis (16^3).
+* The weak-field (Born) limit: pair amplitude and marginal against their
+  first-order closed forms.
 FP64 to 1e-10 relative against the oracle, mixed to 2e-5.
 """
 import numpy as np
@@ -92,3 +94,26 @@ def test_smallest_lengths_3d(S, prec, tol):
         ctx.step()
         for i in range(2):
             assert relerr(ctx.get_psi(i), SWFSolve(prob, i).run()) < tol
+
+
+def test_born_limit_vs_closed_form(S):
+    # the weak-field pair amplitude and marginal on the GPU against the
+    # first-order closed forms (independent of the oracle's stepping)
+    from scipy import integrate
+    import test_oracle_born as B
+    solves = [W.Solve(0, 1, B.P)] + [W.Solve(1, r, [qx, -B.P[1], -B.P[2]]) for qx in B.QX for r in (1, -1)]
+    prob = B.problem(solves)
+    with S.Context(prob, precision="fp64") as ctx:
+        ctx.step()
+        for i in range(1, len(solves)):
+            want = B.omega1(1, B.P, solves[i].spin, solves[i].p)
+            assert abs(ctx.pair(0, i, 1) - want) < 1e-3 * abs(want)
+            assert abs(ctx.pair(0, i, 2) + want) < 1e-3 * abs(want)
+        got = ctx.marginal(0)
+
+    def dens(qx):
+        q = [qx, -B.P[1], -B.P[2]]
+        return sum(abs(B.omega1(1, B.P, r, q)) ** 2 for r in (1, -1)) / (2 * np.pi)
+
+    want, _ = integrate.quad(dens, -12.0, 12.0, limit=400, epsabs=0, epsrel=1e-10)
+    assert abs(got - want) < 1e-3 * want
