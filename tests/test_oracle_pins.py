@@ -169,6 +169,27 @@ def test_rk4_order_four():
     assert 14.0 < ratio < 20.0
 
 
+def test_spatial_refinement_converges_spectrally():
+    # P12: at fixed box and dt, the marginal converges exponentially in the
+    # number of grid points (pseudo-spectral derivative, smooth field): the
+    # error against n = 96 drops by more than 20x for every 8 points added,
+    # which no fixed-order difference scheme does (order k gives 1.25^k at
+    # 32 -> 40), and is at rounding level from n = 64 on
+    L = 40.0
+    F = [W.Term(1, 0.6, W.gauss(1.0), [W.gauss(3.0), W.const(), W.const()]),
+         W.Term(0, 0.4, W.sech2(1.2), [W.ugauss(2.5), W.const(), W.const()])]
+    p = [2 * np.pi * 2 / L, 0.2, 0.0]
+    P = {}
+    for n in (32, 40, 48, 64, 96):
+        prob = W.Problem("c", [W.Grid(1, [n, 1, 1], [L, 1, 1])], [F], [W.Solve(0, 1, p)],
+                         W.Window(-6.0, 6.0, 0.01))
+        sv = SWFSolve(prob, 0)
+        P[n] = ob.marginal(sv, sv.run())
+    e = {n: abs(P[n] - P[96]) for n in (32, 40, 48, 64)}
+    assert e[32] > 20 * e[40] > 400 * e[48]
+    assert e[64] < 1e-12 * P[96]
+
+
 def test_time_only_mode_matches_dop853():
     # A_1(t) = a sech^2(t/tau) -> 0 at both ends: one lattice mode, 4x4 ODE
     a, tau, px, pp = 0.9, 1.5, 0.4, 0.3
