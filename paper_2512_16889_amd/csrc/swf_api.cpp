@@ -1163,10 +1163,10 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
     const int na = (int)ra.size(), nb = (int)rb.size();
     swf::PairArgs a;
     memset(&a, 0, sizeof(a));
-    a.tiles_m = (na + 31) / 32;
-    a.tiles_n = (nb + 31) / 32;
-    a.mp = 32 * a.tiles_m;
-    a.np = 32 * a.tiles_n;
+    a.tiles_m = (na + 63) / 64;       // 64 x 64 output tiles
+    a.tiles_n = (nb + 63) / 64;
+    a.mp = 64 * a.tiles_m;
+    a.np = 64 * a.tiles_n;
     const long long chunks = (ns + 7) / 8;
     const long long want = std::max(1LL, 1024LL / (a.tiles_m * a.tiles_n));
     a.splits = (int)std::min(chunks, want);

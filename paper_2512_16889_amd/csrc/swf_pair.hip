@@ -11,11 +11,12 @@
 // projector Pi applied, as (Pi A)^dag (Pi B) = A^dag Pi B), or a background
 // plane-wave spinor w e^{i K.x} generated on the fly.
 //
-// The contraction runs on the FP64 matrix cores: a workgroup owns a 32 x 32
-// output tile (four waves of 16 x 16) and a range of sites; per site the four
-// spinor components are the k = 4 block of v_mfma_f64_16x16x4, and a complex
-// product is four real ones (re re + im im, re im - im re).  Operands are
-// staged through LDS, 8 sites at a time, with coalesced loads along the
+// The contraction runs on the FP64 matrix cores: a workgroup owns a 64 x 64
+// output tile (four waves of 32 x 32, each 2 x 2 blocks of 16 x 16) and a
+// range of sites, so a matrix up to 64 x 64 reads every state once; per site
+// the four spinor components are the k = 4 block of v_mfma_f64_16x16x4, and a
+// complex product is four real ones (re re + im im, re im - im re).  Operands
+// are staged through LDS, 8 sites at a time, with coalesced loads along the
 // sites.  Workgroups write partial tiles per site range; a second kernel adds
 // them in a fixed order (no atomics: bitwise repeatable).
 #include "swf_reduce.h"
@@ -24,23 +25,32 @@
 namespace swf {
 
 constexpr int PG_THREADS = 256;
-constexpr int PG_T = 32;                  // output tile edge (rows = cols)
+constexpr int PG_T = 64;                  // output tile edge (rows = cols); each wave owns 32 x 32
 constexpr int PG_CS = 8;                  // sites per staged chunk
 constexpr int PG_STR = 4 * PG_T + 1;      // LDS doubles per staged site (one pad)
+constexpr int PG_ITEMS = 2 * PG_T * PG_CS / PG_THREADS;   // staged (side, row, site) items per thread
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-static_assert(PG_T * PG_CS == PG_THREADS, "one staged (row, site) item per thread and side");
+static_assert(PG_ITEMS * PG_THREADS == 2 * PG_T * PG_CS, "whole staged items per thread");
+static_assert(PG_ITEMS % 2 == 0, "half of a thread's items on each side");
 
-// This thread's staged item of a chunk: row r0 + p / PG_CS, site s0 + p % PG_CS.
-// pg_load issues the global loads of a state row (kept in registers while the
-// previous chunk is multiplied); pg_put finishes the item (projector, or the
-// generated plane wave) and writes it to re/im[site][component][row].
+// Staged item j of this thread: side j / (PG_ITEMS/2) (a, then b), row
+// p / PG_CS and site p % PG_CS of that side's chunk, p = (tid + PG_THREADS j)
+// modulo PG_T * PG_CS.  pg_load issues the global loads of a state row (kept
+// in registers while the previous chunk is multiplied); pg_put finishes the
+// item (projector, or the generated plane wave) and writes it to
+// re/im[site][component][row].
+__device__ __forceinline__ void pg_item(int j, int& row, int& ls) {
+    const int p = (threadIdx.x + PG_THREADS * j) % (PG_T * PG_CS);
+    row = p / PG_CS;
+    ls = p % PG_CS;
+}
+
 template <class R>
-__device__ __forceinline__ void pg_load(const PairArgs& a, const PairSide& sd, int r0, long long s0, long long s1,
-                                        double2 (&v)[4]) {
+__device__ __forceinline__ void pg_load(const PairArgs& a, const PairSide& sd, int r0, int row, int ls, long long s0,
+                                        long long s1, double2 (&v)[4]) {
     using C = cpx<R>;
-    const int row = threadIdx.x / PG_CS, ls = threadIdx.x % PG_CS;
     const long long site = s0 + ls;
     const int r = r0 + row;
 #pragma unroll
@@ -52,9 +62,8 @@ __device__ __forceinline__ void pg_load(const PairArgs& a, const PairSide& sd, i
     }
 }
 
-__device__ __forceinline__ void pg_put(const PairArgs& a, const PairSide& sd, int r0, long long s0, long long s1,
-                                       double2 (&v)[4], double* re, double* im) {
-    const int row = threadIdx.x / PG_CS, ls = threadIdx.x % PG_CS;
+__device__ __forceinline__ void pg_put(const PairArgs& a, const PairSide& sd, int r0, int row, int ls, long long s0,
+                                       long long s1, double2 (&v)[4], double* re, double* im) {
     const long long site = s0 + ls;
     const int r = r0 + row;
     if (r < sd.n && site < s1) {
@@ -92,47 +101,84 @@ __device__ __forceinline__ void pg_put(const PairArgs& a, const PairSide& sd, in
 template <class R>
 __global__ void __launch_bounds__(PG_THREADS) pair_gemm_kernel(PairArgs a) {
     __shared__ double are[PG_CS * PG_STR], aim[PG_CS * PG_STR], bre[PG_CS * PG_STR], bim[PG_CS * PG_STR];
+    constexpr int HALF = PG_ITEMS / 2;
     const int ntile = a.tiles_m * a.tiles_n;
     const int tile = blockIdx.x % ntile, split = blockIdx.x / ntile;
     const int r0 = (tile / a.tiles_n) * PG_T, c0 = (tile % a.tiles_n) * PG_T;
     const long long sb = (long long)split * a.per;
     const long long se = sb + a.per < a.ns ? sb + a.per : a.ns;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int q = lane >> 4, i = lane & 15;
-    v4d cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    double2 va[4], vb[4];
-    pg_load<R>(a, a.a, r0, sb, se, va);
-    pg_load<R>(a, a.b, c0, sb, se, vb);
+    // accumulators of the wave's 2 x 2 blocks of 16 x 16
+    v4d cre[2][2], cim[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            cre[bi][bj] = v4d{0, 0, 0, 0};
+            cim[bi][bj] = v4d{0, 0, 0, 0};
+        }
+    int row[PG_ITEMS], ls[PG_ITEMS];
+#pragma unroll
+    for (int j = 0; j < PG_ITEMS; ++j) pg_item(j, row[j], ls[j]);
+    double2 v[PG_ITEMS][4];
+#pragma unroll
+    for (int j = 0; j < PG_ITEMS; ++j) {
+        if (j < HALF) pg_load<R>(a, a.a, r0, row[j], ls[j], sb, se, v[j]);
+        else pg_load<R>(a, a.b, c0, row[j], ls[j], sb, se, v[j]);
+    }
     for (long long s0 = sb; s0 < se; s0 += PG_CS) {
         __syncthreads();   // the previous chunk's operands have been consumed
-        pg_put(a, a.a, r0, s0, se, va, are, aim);
-        pg_put(a, a.b, c0, s0, se, vb, bre, bim);
+#pragma unroll
+        for (int j = 0; j < PG_ITEMS; ++j) {
+            if (j < HALF) pg_put(a, a.a, r0, row[j], ls[j], s0, se, v[j], are, aim);
+            else pg_put(a, a.b, c0, row[j], ls[j], s0, se, v[j], bre, bim);
+        }
         __syncthreads();
         // the next chunk's loads stay in flight during this chunk's products
         if (s0 + PG_CS < se) {
-            pg_load<R>(a, a.a, r0, s0 + PG_CS, se, va);
-            pg_load<R>(a, a.b, c0, s0 + PG_CS, se, vb);
-        }
-#pragma unroll 4
-        for (int ls = 0; ls < PG_CS; ++ls) {
-            // lane (i, q) holds A[m = i][k = q] and B[k = q][n = i]
-            const double ar = are[ls * PG_STR + q * PG_T + wm + i], ai = aim[ls * PG_STR + q * PG_T + wm + i];
-            const double br = bre[ls * PG_STR + q * PG_T + wn + i], bi = bim[ls * PG_STR + q * PG_T + wn + i];
-            // conj(A) B = (ar br + ai bi) + i (ar bi - ai br)
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cre, 0, 0, 0);
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cre, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, cim, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, cim, 0, 0, 0);
-        }
-    }
-    // result element e of lane (i, q): row q + 4 e, column i of the wave's
-    // sub-tile; partials are stored split-fastest for the reduction below
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int row = r0 + wm + q + 4 * e, col = c0 + wn + i;
-        a.part[((long long)row * a.np + col) * a.splits + split] = d2(cre[e], cim[e]);
+            for (int j = 0; j < PG_ITEMS; ++j) {
+                if (j < HALF) pg_load<R>(a, a.a, r0, row[j], ls[j], s0 + PG_CS, se, v[j]);
+                else pg_load<R>(a, a.b, c0, row[j], ls[j], s0 + PG_CS, se, v[j]);
+            }
+        }
+#pragma unroll 2
+        for (int l = 0; l < PG_CS; ++l) {
+            // lane (i, q) holds A[m = i][k = q] and B[k = q][n = i] of each 16 x 16 block
+            const int o = l * PG_STR + q * PG_T;
+            double ar[2], ai[2], br[2], bi_[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                ar[b] = are[o + wm + 16 * b + i];
+                ai[b] = aim[o + wm + 16 * b + i];
+                br[b] = bre[o + wn + 16 * b + i];
+                bi_[b] = bim[o + wn + 16 * b + i];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    // conj(A) B = (ar br + ai bi) + i (ar bi - ai br)
+                    cre[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], cre[x][y], 0, 0, 0);
+                    cre[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], bi_[y], cre[x][y], 0, 0, 0);
+                    cim[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi_[y], cim[x][y], 0, 0, 0);
+                    cim[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], br[y], cim[x][y], 0, 0, 0);
+                }
+        }
     }
+    // result element e of lane (i, q) in block (x, y): row q + 4 e, column i of
+    // that block; partials are stored split-fastest for the reduction below
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = r0 + wm + 16 * x + q + 4 * e, cc = c0 + wn + 16 * y + i;
+                a.part[((long long)rr * a.np + cc) * a.splits + split] = d2(cre[x][y][e], cim[x][y][e]);
+            }
 }
 
 // out[j] = sum over splits of part[j][split]: one wave per output, lanes

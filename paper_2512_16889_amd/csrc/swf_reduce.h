@@ -72,7 +72,7 @@ struct PairArgs {
     double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
     int tiles_m, tiles_n, splits;
     long long per;       // sites per split (a multiple of the staging chunk)
-    int mp, np;          // padded output dimensions (multiples of 32)
+    int mp, np;          // padded output dimensions (multiples of the 64-row tile)
     double2* part;       // [mp][np][splits] partial tiles, then [mp][np] the sum
 };
 

@@ -5,7 +5,7 @@ contractions on the FP64 matrix cores, against
 * the FP64 oracle's pair amplitude, element by element, for every pair of a
   small 2D batch (both forms) and a 1D batch;
 * the per-pair path (swf_amplitude, itself checked against the oracle) for
-  a 3D batch of 37 U x 35 V solves: two 32 x 32 output tiles in each
+  a 3D batch of 70 U x 67 V solves: two 64 x 64 output tiles in each
   direction with ragged edges, and more sites than one split covers;
 * the same in mixed precision (FP32 states, FP64 products and sums);
 and the error paths (order, form, trivial-axis momentum, solve kinds).
@@ -80,14 +80,14 @@ def test_pair_matrix_1d_vs_oracle(S):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
 def test_pair_matrix_3d_tiles_vs_per_pair(S, prec, tol):
-    prob, us, vs = batch(3, (16, 16, 16), (18.0, 18.0, 18.0), 37, 35, seed=3, t_half=1.0)
+    prob, us, vs = batch(3, (16, 16, 16), (18.0, 18.0, 18.0), 70, 67, seed=3, t_half=1.0)
     with S.Context(prob, precision=prec) as ctx:
         ctx.step()
         got1 = ctx.pair_matrix(us, vs, 1)
         got2 = ctx.pair_matrix(us, vs, 2)
         # the per-pair path on a sample that covers every tile and the ragged edges
-        rows = [0, 5, 31, 32, 36]
-        cols = [0, 17, 31, 32, 34]
+        rows = [0, 5, 33, 63, 64, 69]
+        cols = [0, 17, 40, 63, 64, 66]
         ref1 = np.array([[ctx.pair(us[m], vs[n], 1) for n in cols] for m in rows])
         ref2 = np.array([[ctx.pair(us[m], vs[n], 2) for n in cols] for m in rows])
     close(got1[np.ix_(rows, cols)], ref1, tol)
