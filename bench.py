@@ -174,6 +174,42 @@ def cpu_baseline(prob, target_s=15.0):
                       f"numpy/pocketfft FP64, single thread, {el:.1f} s"}
 
 
+def pair_matrix_bench(S, torch, n_each, form=1):
+    """All N x N pair amplitudes of eq. (Nmn) at once (swf_pair_matrix) on the
+    2D 512^2 lattice, against the per-pair path on a sample of pairs."""
+    import numpy as np
+    import swf_workloads as W
+    g = W.Grid(2, [512, 512, 1], [160.0, 160.0, 1.0])
+    rng = np.random.default_rng(0)
+    solves = [W.Solve(0, 1, [float(x) for x in rng.uniform(-0.8, 0.8, 2)] + [0.0]) for _ in range(n_each)]
+    solves += [W.Solve(1, 1, [float(x) for x in rng.uniform(-0.8, 0.8, 2)] + [0.0]) for _ in range(n_each)]
+    prob = W.Problem("pairs", [g], [W.field_gauss_2d()], solves, W.Window(-0.2, 0.2, 0.02))
+    us, vs = list(range(n_each)), list(range(n_each, 2 * n_each))
+    sample = [(0, 0), (n_each // 3, n_each - 1), (n_each - 1, n_each // 2)]
+    with S.Context(prob, precision="fp64") as ctx:
+        ctx.step()
+        ctx.sync()
+        M = ctx.pair_matrix(us, vs, form)              # warm-up (allocates the scratch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = ctx.pair_matrix(us, vs, form)
+        torch.cuda.synchronize()
+        t_matrix = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref = [ctx.pair(us[i], vs[j], form) for i, j in sample]
+        t_pair = (time.perf_counter() - t0) / len(sample)
+    err = max(abs(M[i, j] - r) for (i, j), r in zip(sample, ref)) / float(np.abs(M).max())
+    n_amp = n_each * n_each
+    sites = 512 * 512
+    flops = 2 * 8.0 * n_amp * 4 * sites              # two complex contractions over sites x components
+    return {"metric": "pair amplitudes/s", "value": n_amp / t_matrix, "unit": "amplitudes/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": t_matrix * 1e3, "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"pair-amplitude matrix, {n_each} U x {n_each} V solves, 2D 512^2, form {form}"},
+            "per_pair_path_ms": t_pair * 1e3, "speedup_vs_per_pair": t_pair * n_amp / t_matrix,
+            "matrix_flop": flops, "sample_rel_err_vs_per_pair": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +228,8 @@ def main():
                     help="step in synchronised chunks of STEPS and report each (long jobs)")
     ap.add_argument("--bw-partial", action="store_true",
                     help="also integrate the BW vertices by the partial-integration route (timed with the job)")
+    ap.add_argument("--pair-matrix", type=int, default=0, metavar="N",
+                    help="only time the N x N pair-amplitude matrix on the 2D 512^2 lattice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +251,10 @@ def main():
     import numpy as np
     import torch
     from paper_2512_16889_amd import swf as S
+
+    if args.pair_matrix:
+        print(json.dumps(pair_matrix_bench(S, torch, args.pair_matrix)), flush=True)
+        return
 
     prob, desc = workload(args.workload, args.time_steps)
     steps = prob.window.steps
