@@ -12,8 +12,9 @@ window; it has no past part.  Checked against
   eq. (MparaE);
 * two vertices that share a V solve with different photons (the V
   transforms are redone for the second photon);
-* graph replay (bitwise equal to eager launches), checkpoint and resume of
-  the route's integrals, mixed precision, and the error paths.
+* graph replay (bitwise equal to eager launches), per-instance launches,
+  checkpoint and resume of the route's integrals, mixed precision, and the
+  error paths.
 """
 import numpy as np
 import pytest
@@ -190,3 +191,14 @@ def test_partial_route_errors(S):
         with pytest.raises(S.SwfError) as e:
             ctx.get_bw_state(2)
         assert e.value.code == S.SWF_E_ARG
+
+
+def test_partial_route_per_instance_equals_batched(S):
+    # one launch per solve and pass computes the same numbers as the batched launches
+    prob = shared_v_2d()
+    vals = []
+    for batched in (True, False):
+        with S.Context(prob, precision="fp64", bw_partial=True, batched=batched) as ctx:
+            ctx.step()
+            vals.append(np.array([ctx.bw_partial(v, t) for v in range(2) for t in range(3)]))
+    assert np.abs(vals[0] - vals[1]).max() <= 1e-13 * np.abs(vals[0]).max()
