@@ -157,6 +157,22 @@ def marshal(problem):
     return grids, terms, ffirst, solves, verts, win
 
 
+def workspace_size(problem, precision: str = "fp64", bw_partial: bool = False) -> int:
+    """Device bytes swf_init needs for this problem (swf_workspace_size); allocates nothing."""
+    grids, terms, ffirst, solves, verts, win = marshal(problem)
+    opt = Options()
+    opt.prec = SWF_FP64 if precision == "fp64" else SWF_MIXED
+    opt.batched = 1
+    opt.bw_partial = int(bw_partial)
+    nbytes = C.c_size_t(0)
+    code = _lib.swf_workspace_size(grids, len(problem.grids), terms, ffirst, len(problem.fields), solves,
+                                   len(problem.solves), verts, len(problem.vertices), C.byref(win), C.byref(opt),
+                                   C.byref(nbytes))
+    if code != SWF_OK:
+        raise SwfError(code, _lib.swf_last_error(None).decode())
+    return int(nbytes.value)
+
+
 class Context:
     """One swf_ctx: all solves of a problem, stepped together."""
 
