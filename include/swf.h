@@ -194,6 +194,26 @@ swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]);
 swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
                            double* out);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * matrix as swf_pair_matrix, with its device scratch (row descriptors and
+ * partial output tiles) in a static device array of swf_noalloc_scratch_bytes()
+ * bytes (32 MiB) instead of context memory allocated on the first call.  The
+ * call allocates no device memory.  Each GPU the library runs on holds its own
+ * copy of the array until the process ends (its address is resolved once per
+ * device by swf_init).  Limit: align256(32 (nu + nv)) + 32 mp np bytes must fit
+ * the array, with mp = 64 ceil(nu/64) and np = 64 ceil(nv/64) (every nu, nv up
+ * to 960 x 1024); larger matrices give SWF_E_ARG before any work is queued.
+ * The sums are split over fewer site ranges than swf_pair_matrix uses when the
+ * array is short, so the two agree to rounding, not bitwise.  Every call on a
+ * GPU shares that GPU's array and its contents are overwritten: calls that
+ * overlap on one GPU (from two threads, or on two streams) race, so the caller
+ * must serialise them.  Requirements, outputs and other errors as
+ * swf_pair_matrix. */
+swf_status swf_pair_matrix_noalloc(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves,
+                                   int nv, double* out);
+size_t swf_noalloc_scratch_bytes(void);
+
 enum {
     SWF_P_MARGINAL_E = 0,   /* electron marginal (U_s|Pi_-|U_s) of U solve i           */
     SWF_P_MARGINAL_POS = 1, /* positron marginal (V_s|Pi_+|V_s) of V solve i           */

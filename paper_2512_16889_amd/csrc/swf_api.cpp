@@ -14,6 +14,7 @@
 #include <fstream>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <complex>
 #include <cstdio>
@@ -41,6 +42,30 @@ constexpr int NKIND = 6;                 // kernel-stats kinds (swf_kernel_stats
 constexpr int PROF_POOL = 2048;          // event pairs kept in flight when profiling
 
 const double PI = 3.14159265358979323846;
+
+// Device scratch of swf_pair_matrix_noalloc: row descriptors and partial
+// tiles, in a static array instead of context-owned memory.  Each GPU holds
+// its own copy at its own address (resolved once per device at swf_init);
+// host code must use that address, never the array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 32u << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's scratch array (dev must be current).
+static hipError_t scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 // ------------------------------------------------------------ host Dirac algebra
 struct Spinor { cd c[4]; };
@@ -521,6 +546,7 @@ struct swf_ctx {
     size_t lds_max = 65536;       // dynamic LDS one workgroup may use on this device
     void* pm_buf = nullptr;       // pair-matrix scratch (grown on demand, freed by swf_free)
     size_t pm_bytes = 0;
+    void* noalloc_scratch = nullptr;   // this device's static scratch array (swf_pair_matrix_noalloc)
     std::vector<char> kvalid;
     std::vector<int> bw_done;
     std::vector<cd> bw_cache;     // 3 terms finite + 3 past per vertex
@@ -1156,7 +1182,7 @@ static int pair_amp(swf_ctx* ctx, int i, int j, int form, cd& out) {
 // `role`; PG_BKG rows: their background plane-wave spinors), optionally with
 // Pi_sign applied to k-space states.  Result: na x nb, row-major.
 static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int arole, const std::vector<int>& rb,
-                     int bsrc, int brole, int proj, std::vector<cd>& out) {
+                     int bsrc, int brole, int proj, std::vector<cd>& out, void* ext = nullptr, size_t ext_bytes = 0) {
     const int s0 = ra[0];
     const swf_grid& G = ctx->P.grids[ctx->P.solves[s0].grid];
     const long long ns = ctx->P.hs[s0].nsites;
@@ -1170,6 +1196,16 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
     const long long chunks = (ns + 7) / 8;
     const long long want = std::max(1LL, 1024LL / (a.tiles_m * a.tiles_n));
     a.splits = (int)std::min(chunks, want);
+    const size_t ops_bytes = align256(sizeof(swf::PairOp) * (na + nb));
+    const size_t tile_bytes = sizeof(double2) * (size_t)a.mp * a.np;
+    if (ext) {
+        // a fixed scratch: as many splits as its partial tiles leave room for
+        if (ops_bytes + 2 * tile_bytes > ext_bytes) {
+            ctx->err = "pair matrix too large for the static scratch";
+            return SWF_E_ARG;
+        }
+        a.splits = (int)std::min<long long>(a.splits, (long long)((ext_bytes - ops_bytes) / tile_bytes) - 1);
+    }
     a.per = ((chunks + a.splits - 1) / a.splits) * 8;
     a.splits = (int)((ns + a.per - 1) / a.per);
     a.ns = ns;
@@ -1180,10 +1216,10 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
     }
     a.proj = proj;
     // scratch: row descriptors, then the partial tiles and their sum
-    const size_t ops_bytes = align256(sizeof(swf::PairOp) * (na + nb));
-    const size_t part_bytes = sizeof(double2) * (size_t)(a.splits + 1) * a.mp * a.np;
+    const size_t part_bytes = tile_bytes * (size_t)(a.splits + 1);
     const size_t need = ops_bytes + part_bytes;
-    if (need > ctx->pm_bytes) {
+    void* buf = ext;
+    if (!ext && need > ctx->pm_bytes) {
         HIPCHK(hipStreamSynchronize(ctx->st));
         if (ctx->pm_buf) HIPCHK(hipFree(ctx->pm_buf));
         ctx->pm_buf = nullptr;
@@ -1191,6 +1227,7 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
         HIPCHK(hipMalloc(&ctx->pm_buf, need));
         ctx->pm_bytes = need;
     }
+    if (!ext) buf = ctx->pm_buf;
     std::vector<swf::PairOp> ops(na + nb);
     auto fill = [&](const std::vector<int>& rows, swf::PairOp* o) {
         for (size_t r = 0; r < rows.size(); ++r) {
@@ -1203,8 +1240,8 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
     };
     fill(ra, ops.data());
     fill(rb, ops.data() + na);
-    swf::PairOp* d_ops = (swf::PairOp*)ctx->pm_buf;
-    a.part = (double2*)((char*)ctx->pm_buf + ops_bytes);
+    swf::PairOp* d_ops = (swf::PairOp*)buf;
+    a.part = (double2*)((char*)buf + ops_bytes);
     a.solves = ctx->d_solves();
     a.a = swf::PairSide{d_ops, na, asrc, arole};
     a.b = swf::PairSide{d_ops + na, nb, bsrc, brole};
@@ -1224,7 +1261,7 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
 // background as one x-space contraction, the projected overlap as one
 // k-space contraction, combined with the time phase and dV (dV/N for k space).
 static int pair_matrix(swf_ctx* ctx, int form, const std::vector<int>& us, const std::vector<int>& vs,
-                       std::vector<cd>& out) {
+                       std::vector<cd>& out, void* ext = nullptr, size_t ext_bytes = 0) {
     for (int u : us) {
         int r = check_pair(ctx, u, vs[0]);
         if (r) return r;
@@ -1242,10 +1279,11 @@ static int pair_matrix(swf_ctx* ctx, int form, const std::vector<int>& us, const
         if (r) return r;
     }
     std::vector<cd> gk, gx;
-    int r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_T, vs, swf::PG_STATE, swf::BUF_T, form == 1 ? +1 : -1, gk);
+    int r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_T, vs, swf::PG_STATE, swf::BUF_T, form == 1 ? +1 : -1, gk,
+                      ext, ext_bytes);
     if (r) return r;
-    if (form == 1) r = pair_gemm(ctx, us, swf::PG_BKG, 0, vs, swf::PG_STATE, swf::BUF_Y, 0, gx);
-    else r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_Y, vs, swf::PG_BKG, 0, 0, gx);
+    if (form == 1) r = pair_gemm(ctx, us, swf::PG_BKG, 0, vs, swf::PG_STATE, swf::BUF_Y, 0, gx, ext, ext_bytes);
+    else r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_Y, vs, swf::PG_BKG, 0, 0, gx, ext, ext_bytes);
     if (r) return r;
     const double tin = ctx->P.win.t_in;
     const double dV = ctx->P.hs[us[0]].dV, inv_n = ctx->P.hs[us[0]].inv_n;
@@ -1457,6 +1495,8 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         INITCHK(hipGetDevice(&dev));
         INITCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         ctx->lds_max = (size_t)lds;
+        // this device's copy of the static scratch (swf_pair_matrix_noalloc)
+        INITCHK(scratch_address(dev, &ctx->noalloc_scratch));
     }
     // allow the dynamic LDS every pass kernel of these sizes asks for
     for (const auto* gl : {&P.batched, &P.single})
@@ -1613,8 +1653,8 @@ swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]) {
     return std::isfinite(out[0]) && std::isfinite(out[1]) ? SWF_OK : SWF_E_NONFINITE;
 }
 
-swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
-                           double* out) {
+static swf_status pair_matrix_abi(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
+                                  double* out, void* ext, size_t ext_bytes) {
     if (!ctx || !out || !u_solves || !v_solves || nu <= 0 || nv <= 0) return SWF_E_ARG;
     if (form != 1 && form != 2) {
         ctx->err = "form must be 1 or 2";
@@ -1628,7 +1668,7 @@ swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, 
     if (r) return (swf_status)r;
     std::vector<int> us(u_solves, u_solves + nu), vs(v_solves, v_solves + nv);
     std::vector<cd> res;
-    r = pair_matrix(ctx, form, us, vs, res);
+    r = pair_matrix(ctx, form, us, vs, res, ext, ext_bytes);
     if (r) return (swf_status)r;
     r = leave(ctx);
     if (r) return (swf_status)r;
@@ -1640,6 +1680,35 @@ swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, 
     }
     return finite ? SWF_OK : SWF_E_NONFINITE;
 }
+
+swf_status swf_pair_matrix(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
+                           double* out) {
+    return pair_matrix_abi(ctx, form, u_solves, nu, v_solves, nv, out, nullptr, 0);
+}
+
+swf_status swf_pair_matrix_noalloc(swf_ctx* ctx, int form, const int* u_solves, int nu, const int* v_solves, int nv,
+                                   double* out) {
+    if (!ctx) return SWF_E_ARG;
+    if (!ctx->noalloc_scratch) {
+        ctx->err = "the static scratch of this device was not resolved at swf_init";
+        return SWF_E_HIP;
+    }
+    if (nu > 0 && nv > 0) {
+        // the row descriptors and at least two padded output tiles (one split and the sum) must fit
+        const size_t mp = 64 * (((size_t)nu + 63) / 64), np = 64 * (((size_t)nv + 63) / 64);
+        const size_t need = align256(sizeof(swf::PairOp) * ((size_t)nu + nv)) + 2 * sizeof(double2) * mp * np;
+        if (need > NOALLOC_SCRATCH_BYTES) {
+            char b[200];
+            snprintf(b, sizeof(b), "a %d x %d pair matrix needs %zu bytes of scratch, more than the static %zu",
+                     nu, nv, need, NOALLOC_SCRATCH_BYTES);
+            ctx->err = b;
+            return SWF_E_ARG;
+        }
+    }
+    return pair_matrix_abi(ctx, form, u_solves, nu, v_solves, nv, out, ctx->noalloc_scratch, NOALLOC_SCRATCH_BYTES);
+}
+
+size_t swf_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out) {
     if (!ctx || !out) return SWF_E_ARG;

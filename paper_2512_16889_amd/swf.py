@@ -89,6 +89,11 @@ _lib.swf_steps.argtypes = [C.c_void_p, _P(C.c_int), _P(C.c_int)]
 _lib.swf_supported_n.argtypes = [C.c_int]
 _lib.swf_pair_matrix.argtypes = [C.c_void_p, C.c_int, _P(C.c_int), C.c_int, _P(C.c_int), C.c_int, _P(C.c_double)]
 _lib.swf_pair_matrix.restype = C.c_int
+_lib.swf_pair_matrix_noalloc.argtypes = [C.c_void_p, C.c_int, _P(C.c_int), C.c_int, _P(C.c_int), C.c_int,
+                                         _P(C.c_double)]
+_lib.swf_pair_matrix_noalloc.restype = C.c_int
+_lib.swf_noalloc_scratch_bytes.argtypes = []
+_lib.swf_noalloc_scratch_bytes.restype = C.c_size_t
 _lib.swf_tune_report.argtypes = [C.c_void_p]
 _lib.swf_tune_report.restype = C.c_char_p
 _lib.swf_last_error.argtypes = [C.c_void_p]
@@ -99,13 +104,18 @@ _lib.swf_free.restype = None
 EXPORTED = ["swf_workspace_size", "swf_init", "swf_step", "swf_reset", "swf_sync", "swf_amplitude", "swf_probability",
             "swf_diagnostics", "swf_get_psi", "swf_set_psi", "swf_get_bw_state", "swf_set_bw_state",
             "swf_apply_op", "swf_kernel_stats", "swf_reset_stats", "swf_supported_n", "swf_steps",
-            "swf_tune_report", "swf_last_error", "swf_free", "swf_pair_matrix"]
+            "swf_tune_report", "swf_last_error", "swf_free", "swf_pair_matrix", "swf_pair_matrix_noalloc",
+            "swf_noalloc_scratch_bytes"]
 
 
 class SwfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"swf status {code}: {msg}")
         self.code = code
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(_lib.swf_noalloc_scratch_bytes())
 
 
 def supported_n(n: int) -> bool:
@@ -329,13 +339,14 @@ class Context:
         return self._from_lib(out, i)
 
     # ---------------------------------------------------------------- profiling
-    def pair_matrix(self, u_solves, v_solves, form: int = 1):
-        """Omega(u_solves[m], v_solves[n]) for every pair, as an nu x nv complex array."""
+    def pair_matrix(self, u_solves, v_solves, form: int = 1, noalloc: bool = False):
+        """Omega(u_solves[m], v_solves[n]) for every pair, as an nu x nv complex array
+        (noalloc: through swf_pair_matrix_noalloc, scratch in the static device array)."""
         us = (C.c_int * len(u_solves))(*[int(i) for i in u_solves])
         vs = (C.c_int * len(v_solves))(*[int(i) for i in v_solves])
         out = np.zeros(2 * len(u_solves) * len(v_solves), dtype=np.float64)
-        self._check(_lib.swf_pair_matrix(self._ctx, int(form), us, len(u_solves), vs, len(v_solves),
-                                         out.ctypes.data_as(_P(C.c_double))))
+        fn = _lib.swf_pair_matrix_noalloc if noalloc else _lib.swf_pair_matrix
+        self._check(fn(self._ctx, int(form), us, len(u_solves), vs, len(v_solves), out.ctypes.data_as(_P(C.c_double))))
         return (out[0::2] + 1j * out[1::2]).reshape(len(u_solves), len(v_solves))
 
     def kernel_stats(self, kind: int):
