@@ -38,6 +38,8 @@ orthogonality identities, charge-conjugation symmetry, RK4 convergence
 order, the exact spin structure of the BW amplitude for E(t,x) fields and
 the t_in independence of past + finite BW terms.
 
-Parity unpinned: the absorbing-boundary mask (not part of the paper; it is
-off for every pin and parity case) has only a self-consistency check.
+The absorbing-boundary mask (not part of the paper; off for every other pin
+and parity case) is pinned by a wave packet leaving the box: inside the
+unmasked interior the masked box gives the wave of a periodic box twice as
+long, before and after the packet crosses the edge.
 """

@@ -48,7 +48,9 @@ class Lattice:
         m_j = 1 - strength * sin^2(pi/2 * (cells - d)/cells) within ``cells``
         of either edge (d = distance in cells to the nearest edge), 1 inside.
         Not part of the paper (its scattered waves are simply kept inside a
-        periodic box); off whenever cells == 0."""
+        periodic box); off whenever cells == 0.  Pinned as an absorbing layer:
+        an outgoing packet leaves the interior as it would on a periodic box
+        twice as long (no reflection, no wrap-around)."""
         m = np.ones(self.shape)
         if cells <= 0:
             return m

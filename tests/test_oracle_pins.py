@@ -311,3 +311,49 @@ def test_charge_balance_over_all_lattice_modes():
             Pp += P
     assert Pe > 1e-4
     assert Pp == pytest.approx(Pe, rel=1e-6)
+
+
+def _free_packet_run(n, L, cells, strength, checkpoints, k0=2.0, sigma=4.0, dt=0.05):
+    """A positive-energy Gaussian packet u(k0) e^{i k0 x - x^2/sigma^2}
+    evolved freely (A = 0, so psi_s obeys the free Dirac equation) on a 1D
+    box, with the boundary mask on or off; returns (x, psi) at the given step
+    counts."""
+    t_half = 0.5 * dt * checkpoints[-1]
+    g = W.Grid(1, [n, 1, 1], [L, 1.0, 1.0], cells, strength)
+    prob = W.Problem("absorb", [g], [[]], [W.Solve(0, 1, [0.4, 0.0, 0.0])], W.Window(-t_half, t_half, dt))
+    sv = SWFSolve(prob, 0)
+    x = sv.lat.X[0]
+    y = dirac.u_spinor(1, np.array([k0, 0.0, 0.0]))[:, None] * \
+        np.exp(1j * k0 * x - x ** 2 / sigma ** 2)[None]
+    out, done = [], 0
+    for c in checkpoints:
+        y = sv.run(y, start=done, count=c - done)
+        done = c
+        out.append(y.copy())
+    return x, out
+
+
+def test_absorbing_mask_matches_a_larger_periodic_box():
+    """The boundary mask (not part of the paper) is meant to make a periodic box
+    act like an unbounded one for waves leaving it.  Pin: a packet moving at
+    v = 0.89 on a box of length L = 80 with the mask (24 cells, strength 0.05)
+    gives, inside the unmasked interior, the same wave as on a box of 2L without
+    mask, both while it is still inside (the mask must not touch it) and after
+    it has left (it must be absorbed, not reflected): 1e-4 of the packet's
+    height.  Without the mask it wraps round the box L and comes back into the
+    interior at O(1)."""
+    n, L, cells = 128, 80.0, 24
+    steps = [200, 2000]           # t = 10: packet inside; t = 100: it crossed an edge (and, on L, would wrap)
+    x1, masked = _free_packet_run(n, L, cells, 0.05, steps)
+    x2, big = _free_packet_run(2 * n, 2 * L, 0, 0.0, steps)
+    _, bare = _free_packet_run(n, L, 0, 0.0, steps)
+    inner = L / 2 - cells * L / n
+    s1, s2 = np.abs(x1) < inner, np.abs(x2) < inner
+    assert np.allclose(x1[s1], x2[s2])
+    for k in range(2):
+        err = np.abs(masked[k][:, s1] - big[k][:, s2]).max()
+        assert err < 1e-4, (k, err)
+    # at the end the packet has left the interior of the large box ...
+    assert np.abs(big[1][:, s2]).max() < 1e-5
+    # ... while without the mask it has wrapped back into that of the small one
+    assert np.abs(bare[1][:, s1] - big[1][:, s2]).max() > 0.1
