@@ -127,6 +127,12 @@ typedef struct {
                                state-sized buffers, and every RK4 stage adds, per vertex,
                                the source term in x space, four full forward transforms
                                and two reductions; 0: off                              */
+    int check_every;        /* > 0: after every check_every-th step (by step index) swf_step
+                               reads every psi_s once on the device and records the first
+                               step and solve holding a NaN or an Inf; a swf_step call that
+                               queued a check then waits for its work and returns
+                               SWF_E_NONFINITE if one was seen (the steps are still taken;
+                               swf_last_error names the step and solve).  0: no check   */
 } swf_options;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */
@@ -148,9 +154,16 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms,
                     const swf_window* window, const swf_options* opt, swf_ctx** out);
 
 /* Enqueue n_steps RK4 steps of every solve (and of the BW vertex integrals)
- * toward t_in on the context's stream.  Asynchronous: returns after enqueueing.
- * *steps_left (optional) receives the remaining step count.
- * SWF_E_ORDER if n_steps exceeds the steps left; SWF_E_ARG if n_steps < 0. */
+ * toward t_in on the context's stream.  One step is classical RK4 with
+ * h = -dt of eq. (scatDirac) multiplied by gamma^0 (section "Numerical
+ * approach": spatial derivatives through FFTs, the vector of spinors stepped
+ * in time), each BW vertex's finite-time integral, eq. (Mabfinite), carried
+ * along as an extra component of the stepped state.  Asynchronous: returns
+ * after enqueueing, unless options.check_every > 0 and a check fell in the
+ * call (then it waits for the call's work).  *steps_left (optional) receives
+ * the remaining step count.  SWF_E_ORDER if n_steps exceeds the steps left;
+ * SWF_E_ARG if n_steps < 0; SWF_E_NONFINITE if the in-loop check saw a NaN or
+ * an Inf. */
 swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left);
 
 /* Return every solve to psi_s(t_out) = 0 at step 0 and clear the BW integrals,
@@ -220,15 +233,22 @@ enum {
     SWF_P_PAIR = 2,         /* |Omega_1(i,j)|^2                                        */
     SWF_P_BW = 3            /* |M|^2 of vertex i                                       */
 };
-/* Probabilities at t_in (SWF_E_ORDER before t_in).  Marginals are densities in
- * d^d p/(2 pi)^d per unit transverse volume. */
+/* Probabilities at t_in (SWF_E_ORDER before t_in).  PAIR: the pair number
+ * N = |Omega|^2 of eq. (Nmn) (form 1).  MARGINAL_E / MARGINAL_POS: the sum of
+ * eq. (Nmn)'s N over every partner state, which the completeness of the free
+ * states turns into the energy-projected norm of the scattered wave at t_in
+ * (same inner products as eq. (Nmn)).  BW: |M|^2 of the vertex amplitude of the
+ * Breit-Wheeler section (eqs. (Mabfinite), (MScatScatPast) and partners).
+ * Marginals are densities in d^d p/(2 pi)^d per unit transverse volume. */
 swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out);
 
 /* Diagnostics of solve i at the current time t = t_out - step*dt, accumulated in
- * double: out[0] = (psi_s|psi_s), out[1] = 2 Re(psi_b|psi_s) (for a momentum on the
- * lattice out[0] + out[1] stays 0: the full wave function keeps its norm),
- * out[2] = max |psi_s component|, out[3] = 1 if every value is finite else 0.
- * Returns SWF_E_NONFINITE if out[3] == 0. */
+ * double: out[0] = (psi_s|psi_s), out[1] = 2 Re(psi_b|psi_s) with the inner
+ * product (psi|phi) = int d^3x psi^dagger phi of eq. (Nmn)'s text.  The full
+ * psi = psi_b + psi_s solves the Dirac equation (eq. (scatDirac) with
+ * psi_s(t_out) = 0), which keeps its norm, so for a momentum on the lattice
+ * out[0] + out[1] stays 0.  out[2] = max |psi_s component|, out[3] = 1 if every
+ * value is finite else 0.  Returns SWF_E_NONFINITE if out[3] == 0. */
 swf_status swf_diagnostics(swf_ctx* ctx, int i, double out[4]);
 
 /* Copy the scattered wave of solve i to / from host memory as complex double,

@@ -465,6 +465,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     }
     // ---- groups and work items
     if (opt->chunk < 0) FAIL(SWF_E_ARG, "chunk must be >= 0");
+    if (opt->check_every < 0) FAIL(SWF_E_ARG, "check_every must be >= 0");
     for (int g = 0; g < n_grids; ++g) {
         std::vector<int> all;
         for (int i = 0; i < n_solves; ++i) if (P.solves[i].grid == g) all.push_back(i);
@@ -569,6 +570,8 @@ struct swf_ctx {
     void* d_ctab() { return arena + P.off_ctab; }
     int2* d_items() { return (int2*)(arena + P.off_items); }
     int* d_step() { return (int*)(arena + P.off_step); }
+    // first (step, solve) of a non-finite value seen by the in-loop check, as ~key (0: none)
+    unsigned long long* d_flag() { return (unsigned long long*)(arena + P.off_step + 64); }
     double2* d_M() { return (double2*)(arena + P.off_M); }
     double2* d_part() { return (double2*)(arena + P.off_part); }
     double2* d_red() { return (double2*)(arena + P.off_red); }
@@ -1551,9 +1554,24 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
     }
     int r = enter(ctx);
     if (r) return (swf_status)r;
+    const int K = ctx->opt.check_every;
+    unsigned long long* flag = ctx->d_flag();
+    bool checked = false;
+    // the in-loop finite check after step index `at` (a multiple of K)
+    auto check = [&](int at) -> int {
+        HIPCHK(swf::launch_finite_check(ctx->P.fp64, ctx->d_solves(), (int)ctx->P.solves.size(), at, flag, ctx->st));
+        checked = true;
+        return SWF_OK;
+    };
     if (line_path(ctx)) {
-        r = line_steps(ctx, n_steps);
-        if (r) return (swf_status)r;
+        for (int done = 0; done < n_steps;) {
+            int c = n_steps - done;
+            if (K > 0) c = std::min(c, K - (ctx->step + done) % K);
+            r = line_steps(ctx, c);
+            if (r) return (swf_status)r;
+            done += c;
+            if (K > 0 && (ctx->step + done) % K == 0 && (r = check(ctx->step + done))) return (swf_status)r;
+        }
     } else {
         r = refresh_T(ctx);
         if (r) return (swf_status)r;
@@ -1564,6 +1582,7 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
                 r = enqueue_step(ctx);
                 if (r) return (swf_status)r;
             }
+            if (K > 0 && (ctx->step + i + 1) % K == 0 && (r = check(ctx->step + i + 1))) return (swf_status)r;
         }
     }
     if (n_steps > 0) {
@@ -1574,6 +1593,19 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
     r = leave(ctx);
     if (r) return (swf_status)r;
     if (steps_left) *steps_left = ctx->P.steps - ctx->step;
+    if (checked) {
+        unsigned long long key = 0;
+        HIPCHK(hipMemcpyAsync(&key, flag, sizeof(key), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        if (key) {
+            key = ~key;
+            char b[160];
+            snprintf(b, sizeof(b), "non-finite value in solve %u, first seen at the check after step %llu",
+                     (unsigned)(key & 0xffffffffu), key >> 32);
+            ctx->err = b;
+            return SWF_E_NONFINITE;
+        }
+    }
     return SWF_OK;
 }
 

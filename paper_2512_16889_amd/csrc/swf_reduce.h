@@ -85,6 +85,8 @@ hipError_t launch_bw2_kss(int fp64, const BwArgs& a, int blocks, hipStream_t st)
 hipError_t launch_bw2_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_tick(int* step, hipStream_t st);
 hipError_t launch_advance(int* step, int n, hipStream_t st);
+hipError_t launch_finite_check(int fp64, const SolveDev* solves, int nsolves, int step, unsigned long long* flag,
+                               hipStream_t st);
 
 struct SizeKernels;
 // Kernel table of an FFT length for single (fp64 = 0) or double precision, NULL if unsupported.

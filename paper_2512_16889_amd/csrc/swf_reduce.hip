@@ -482,6 +482,28 @@ __global__ void bw2_accum_kernel(BwArgs a, int nblk) {
     *M = dadd(*M, dsc(s, -a.dt / 6.0));
 }
 
+// In-loop check of the state: *flag becomes the largest ~((step << 32) | s)
+// over the solves s whose psi_s (Y array) holds a NaN or an Inf, so the host
+// reads back the first step and solve where one appeared (0: none so far).
+// One read of every state, one atomic per wave that found a bad value.
+template <class R>
+__global__ void __launch_bounds__(RED_THREADS) finite_kernel(const SolveDev* solves, int nsolves, int step,
+                                                            unsigned long long* flag) {
+    for (int s = 0; s < nsolves; ++s) {
+        const SolveDev* S = solves + s;
+        const nv2<R>* y = reinterpret_cast<const nv2<R>*>(S->buf[BUF_Y]);
+        const long long n = 4 * S->nsites;
+        bool bad = false;
+        for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < n;
+             i += (long long)gridDim.x * RED_THREADS) {
+            const nv2<R> v = y[i];
+            bad = bad || !(isfinite(v.x) && isfinite(v.y));
+        }
+        if (__any(bad) && (threadIdx.x % warpSize) == 0)
+            atomicMax(flag, ~(((unsigned long long)step << 32) | (unsigned)s));
+    }
+}
+
 __global__ void tick_kernel(int* step, int n) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(step, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -540,6 +562,15 @@ hipError_t launch_bw2_accum(const BwArgs& a, int nblk, hipStream_t st) {
 }
 
 hipError_t launch_tick(int* step, hipStream_t st) { return launch_advance(step, 1, st); }
+
+hipError_t launch_finite_check(int fp64, const SolveDev* solves, int nsolves, int step, unsigned long long* flag,
+                               hipStream_t st) {
+    if (fp64)
+        hipLaunchKernelGGL(finite_kernel<double>, dim3(1024), dim3(RED_THREADS), 0, st, solves, nsolves, step, flag);
+    else
+        hipLaunchKernelGGL(finite_kernel<float>, dim3(1024), dim3(RED_THREADS), 0, st, solves, nsolves, step, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_advance(int* step, int n, hipStream_t st) {
     hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, st, step, n);

@@ -64,7 +64,8 @@ class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int), ("batched", C.c_int),
                 ("profile", C.c_int), ("tune", C.c_int), ("tune_cache", C.c_char_p), ("chunk", C.c_int),
-                ("force_variant", C.c_int), ("persistent", C.c_int), ("bw_partial", C.c_int)]
+                ("force_variant", C.c_int), ("persistent", C.c_int), ("bw_partial", C.c_int),
+                ("check_every", C.c_int)]
 
 
 _P = C.POINTER
@@ -189,7 +190,7 @@ class Context:
     def __init__(self, problem, precision: str = "fp64", use_graph: bool = False, batched: bool = True,
                  profile: bool = False, device_workspace: bool = True, tune: bool = False,
                  tune_cache: str | None = None, chunk: int = 0, variant: int | None = None,
-                 persistent: bool = True, bw_partial: bool = False):
+                 persistent: bool = True, bw_partial: bool = False, check_every: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the SWF solver runs on the GPU only; no device is visible")
         self.problem = problem
@@ -205,6 +206,7 @@ class Context:
         self.opt.force_variant = 0 if variant is None else int(variant) + 1
         self.opt.persistent = int(persistent)
         self.opt.bw_partial = int(bw_partial)
+        self.opt.check_every = int(check_every)
         self._tune_cache = tune_cache.encode() if tune_cache else None
         self.opt.tune_cache = self._tune_cache
         self.opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)

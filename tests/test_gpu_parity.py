@@ -246,3 +246,25 @@ def test_nonfinite_detected(S):
         with pytest.raises(S.SwfError) as e:
             c.diagnostics(0)
         assert e.value.code == S.SWF_E_NONFINITE
+
+
+@pytest.mark.parametrize("dim,persistent", [(1, True), (1, False), (2, False)])
+def test_in_loop_nonfinite_check(S, dim, persistent):
+    """options.check_every: a NaN planted in one solve at step 3 is reported by
+    swf_step at the first check after it (step 4 with checks every 2 steps),
+    naming that solve; a clean run of the same context passes every check."""
+    n, L = ((64,), (40.0,)) if dim == 1 else ((32, 32), (20.0, 20.0))
+    prob = problem(dim, n, L, kinds=(0,), spins=(1, -1))
+    shape = (4,) + n
+    with S.Context(prob, precision="fp64", check_every=2, persistent=persistent) as c:
+        assert c.step(6) == prob.window.steps - 6          # clean: every check passes
+        c.reset()
+        psi = np.zeros(shape, dtype=complex)
+        psi[(2,) + (5,) * dim] = np.inf
+        c.set_psi(1, psi, 3)
+        c.set_psi(0, np.zeros(shape, dtype=complex), 3)
+        with pytest.raises(S.SwfError) as e:
+            c.step(4)
+        assert e.value.code == S.SWF_E_NONFINITE
+        assert "solve 1" in str(e.value) and "after step 4" in str(e.value)
+        assert c.steps()[1] == 7                            # the steps were still taken
