@@ -1007,9 +1007,9 @@ static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
         auto it = cache.find(key);
         const int dim = ctx->P.grids[g.grid].dim;
         if (it != cache.end()) {
-            g.vr = std::min(it->second[0], swf::NVAR - 1);
-            g.vy = std::min(it->second[1], swf::NVAR - 1);
-            g.vz = std::min(it->second[2], swf::NVAR - 1);
+            g.vr = std::min(it->second[0], g.k[0]->nvar - 1);
+            g.vy = dim >= 2 ? std::min(it->second[1], g.k[1]->nvar_col - 1) : 0;
+            g.vz = dim >= 3 ? std::min(it->second[2], g.k[2]->nvar_col - 1) : 0;
             rep << key << ": cached " << g.vr << " " << g.vy << " " << g.vz << "\n";
             continue;
         }
@@ -1029,7 +1029,7 @@ static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
             const int mode = (axis == dim - 1) ? swf::COL_H0 : swf::COL_FWD;
             best = 1e30f;
             bv = 0;
-            for (int v = 0; v < g.k[axis]->nvar; ++v) {
+            for (int v = 0; v < g.k[axis]->nvar_col; ++v) {
                 (axis == 1 ? g.vy : g.vz) = v;
                 float ms = 0;
                 int r = time_it(ctx, [&] { return col_pass(ctx, g, axis, mode, swf::BUF_T, 4); }, reps, &ms);
@@ -1526,9 +1526,13 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     ctx->bw_done.assign(P.hv.size(), 0);
     ctx->bw_cache.assign(6 * P.hv.size(), cd(0));
     if (opt->force_variant > 0) {
-        const int v = std::min(opt->force_variant - 1, swf::NVAR - 1);
+        const int v = opt->force_variant - 1;
         for (auto* gl : {&P.batched, &P.single})
-            for (auto& g : *gl) g.vr = g.vy = g.vz = v;
+            for (auto& g : *gl) {
+                g.vr = std::min(v, g.k[0]->nvar - 1);
+                g.vy = g.k[1] ? std::min(v, g.k[1]->nvar_col - 1) : 0;
+                g.vz = g.k[2] ? std::min(v, g.k[2]->nvar_col - 1) : 0;
+            }
     } else if (opt->tune && !line_path(ctx)) {
         int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
         if (rr) return fail(rr);

@@ -59,8 +59,10 @@ template <int N> constexpr int half_t() {
     constexpr int T = FftPlan<N>::T;
     return (T % 2 == 0 && 2 * N / T <= 16 && plan_ok<N, T / 2>()) ? T / 2 : T;
 }
-constexpr int NVAR = 4;
+constexpr int NVAR = 6;       // row-pass variants (4, 5: component-split)
+constexpr int NVAR_COL = 4;   // column-pass variants
 template <int N> constexpr int nvar() { return N >= 256 ? NVAR : 1; }
+template <int N> constexpr int nvar_col() { return N >= 256 ? NVAR_COL : 1; }
 constexpr size_t LDS_CAP = 72 * 1024;
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
@@ -466,6 +468,222 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
     }
 }
 
+// ------------------------------------------------------------------ component-split row pass
+// The RK4 stage pass with one spinor component per thread.  T threads share
+// each component line (E = N/T points each), so a thread holds E points of
+// the transform instead of 4E and needs a quarter of the registers.  The
+// stage epilogue couples the four components of a site (A-slash mixes them):
+// after the inverse x transform every thread leaves its points in LDS, each
+// thread then finishes the sites t + T m, m = q, q+4, ... of its lane (all
+// four components of each), writes the next stage input back in place, and
+// after a barrier every thread reads its own component again and transforms
+// it forward.
+//   v4: the few-points-per-thread plan, 256 threads per block;
+//   v5: the default plan, 128 threads per block (fewer exchange steps).
+template <class R, int N, int V> struct RowCsVar {
+    static constexpr bool SMALL = V == 4 && has_small_plan<N>();
+    using PL = typename PlanSel<N, SMALL>::type;
+    static constexpr int T = PL::T;
+    static constexpr int E = N / T;
+    static constexpr int ROWS = imax(1, (V == 4 ? 256 : 128) / (4 * T));
+    static constexpr int THREADS = 4 * T * ROWS;
+    using Lay = RowLay<N, 4 * ROWS>;
+    static constexpr size_t BYTES = (size_t)4 * ROWS * Lay::STRIDE * sizeof(cpx<R>);
+    // waves per SIMD the LDS of a compute unit (160 KiB) allows; the compiler
+    // is asked to fit that many (at most 4) in the register file
+    static constexpr int BLOCKS_PER_CU = (int)(163840 / (BYTES + N * sizeof(cpx<R>) + 512));
+    static constexpr int WAVES = imax(1, imin(4, BLOCKS_PER_CU * (THREADS / 64) / 4));
+    static_assert(plan_ok<N, T, PL>(), "component-split row variant violates the FFT plan constraints");
+    static_assert(THREADS <= 1024, "component-split row block too large");
+};
+
+template <class R, int N, int V, int STAGE>
+__global__ void __launch_bounds__((RowCsVar<R, N, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(RowCsVar<R, N, V>::WAVES, 8))) row_cs_kernel(PassArgs a) {
+    using C = cpx<R>;
+    using VC = RowCsVar<R, N, V>;
+    constexpr int T = VC::T;
+    constexpr int E = VC::E;
+    constexpr int ROWS = VC::ROWS;
+    using Lay = typename VC::Lay;
+    using PL = typename VC::PL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    __shared__ R sh_fyz[ROWS][MAX_TERMS];
+    __shared__ int sh_mu[MAX_TERMS];
+    __shared__ long long sh_tab[MAX_TERMS];
+    __shared__ C sh_wc[4];
+    __shared__ C sh_phyz[ROWS];
+    __shared__ C tw[N];
+
+    const int tid = threadIdx.x;
+    const int t = tid % T;
+    const int q = (tid / T) % 4;
+    const int line = tid / (4 * T);
+    const int cl = 4 * line + q;          // LDS line of this thread's component
+    const int2 it = a.items[blockIdx.x];
+    const SolveDev* __restrict__ S = a.solves + it.x;
+    const int row = it.y * ROWS + line;
+    const bool act = row < S->nrows;
+    const int rowc = act ? row : 0;
+    const long long base = (long long)rowc * N;
+    const long long ns = S->nsites;
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
+    // twiddles: first read after the first exchange's barriers
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[0] + i);
+    const int n0 = S->n[0], n1 = S->n[1];
+    const int yy = rowc % n1, zz = rowc / n1;
+
+    C v[1][E];
+    {
+        gptr<const nv2<R>> p = cview<R>(S->buf[BUF_T]) + base + q * ns + t;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[0][m] = gload_nt<C>(p, T * m);
+    }
+    // per-line constants of the stage time, published by the transform's barriers
+    constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
+    const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+    const int nterm = S->nterm;
+    if (q == 0) {
+        for (int j = t; j < nterm; j += T) {
+            const TermDev tm = a.terms[S->term0 + j];
+            const double coef = tm.amp * profile_t(tm.ft_type, tm.c, tm.w, tm.k, tm.phi, ts);
+            sh_fyz[line][j] = (R)coef * rtab[tm.tab + n0 + yy] * rtab[tm.tab + n0 + n1 + zz];
+            if (line == 0) {
+                sh_mu[j] = tm.mu;
+                sh_tab[j] = tm.tab;
+            }
+        }
+        if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
+    }
+    if (tid < 4) {
+        double sn, cs;
+        sincos(-S->E * ts, &sn, &cs);
+        const double wr = S->w[2 * tid], wi = S->w[2 * tid + 1];
+        sh_wc[tid] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
+    }
+    if (a.h0row) {
+        // one-dimensional grid: -i H0(k)/N couples the components of a mode, so
+        // the k-space line goes through LDS first (sites as in the epilogue)
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[Lay::addr(0, cl, t + T * m)] = v[0][m];
+        __syncthreads();
+        const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], sn = (R)S->inv_n;
+        const double dk = S->dk[0];
+#pragma unroll
+        for (int j = 0; j < (E + 3) / 4; ++j) {
+            const int m = q + 4 * j;
+            if (m < E) {
+                const int idx = t + T * m;
+                C w[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) w[c] = lds[Lay::addr(0, 4 * line + c, idx)];
+                apply_h0(w[0], w[1], w[2], w[3], (R)(dk * kindex(idx, N)), Ky, Kz, sn);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) lds[Lay::addr(0, 4 * line + c, idx)] = w[c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[0][m] = lds[Lay::addr(0, cl, t + T * m)];
+    }
+    fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, cl, tw);
+    // the inverse transform into LDS, natural order
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) lds[Lay::addr(0, cl, t + T * m)] = v[0][m];
+    __syncthreads();
+
+    // ---- stage epilogue of the sites t + T m, m = q, q + 4, ...
+    const R h = (R)(-a.dt);
+    const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0), third = (R)(1.0 / 3.0);
+    const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
+    const C phyz = sh_phyz[line];
+    const long long mask = S->mask;
+    const R myz = (STAGE == 3 && mask >= 0) ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
+    gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base;
+    gptr<const nv2<R>> py = cview<R>(S->buf[BUF_Y]) + base;
+    gptr<const nv2<R>> pacc = cview<R>(S->buf[BUF_ACC]) + base;
+    gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base;
+    gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base;
+    gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base;
+#pragma unroll
+    for (int j = 0; j < (E + 3) / 4; ++j) {
+        const int m = q + 4 * j;
+        if (m < E) {
+            const int idx = t + T * m;
+            C yi[4], kin[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) yi[c] = gload_nt<C>(pin, c * ns + idx);
+            C y0[4];
+            if constexpr (STAGE == 1 || STAGE == 2) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) y0[c] = gload_nt<C>(py, c * ns + idx);
+            } else if constexpr (STAGE == 3) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) y0[c] = gload_nt<C>(pacc, c * ns + idx);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) kin[c] = lds[Lay::addr(0, 4 * line + c, idx)];
+            R A[4] = {(R)0, (R)0, (R)0, (R)0};
+#pragma unroll
+            for (int jt = 0; jt < MAX_TERMS; ++jt) {
+                if (jt < nterm) {
+                    const R f = sh_fyz[line][jt] * rtab[sh_tab[jt] + idx];
+                    const int mu = sh_mu[jt];
+                    A[0] += mu == 0 ? f : (R)0;
+                    A[1] += mu == 1 ? f : (R)0;
+                    A[2] += mu == 2 ? f : (R)0;
+                    A[3] += mu == 3 ? f : (R)0;
+                }
+            }
+            const C ph = cmul(gload<C>(ctab, S->ph + idx), phyz);
+            C sv[4], vs[4], out[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sv[c] = cadd(yi[c], cmul(wc[c], ph));
+            apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const C k = cadd(kin[c], cmul_mi(vs[c]));
+                // Classical RK4 with the accumulator written once (see row_kernel)
+                if constexpr (STAGE == 0) {
+                    out[c] = cadd(yi[c], cscale(k, h2));                                   // y_2
+                    if (act) gstore_nt<C>(wys, c * ns + idx, out[c]);
+                } else if constexpr (STAGE == 1) {
+                    out[c] = cadd(y0[c], cscale(k, h2));                                   // y_3
+                    const C acc = cscale(csub(cadd(yi[c], cscale(out[c], (R)2)), y0[c]), third);
+                    if (act) {
+                        gstore_nt<C>(wacc, c * ns + idx, acc);
+                        gstore_nt<C>(wys, c * ns + idx, out[c]);
+                    }
+                } else if constexpr (STAGE == 2) {
+                    out[c] = cadd(y0[c], cscale(k, h));                                    // y_4
+                    if (act) gstore_nt<C>(wys, c * ns + idx, out[c]);
+                } else {
+                    const R mk = mask >= 0 ? rtab[mask + idx] * myz : (R)1;
+                    out[c] = cscale(cadd(cadd(y0[c], cscale(yi[c], third)), cscale(k, h6)), mk);
+                    if (act) gstore_nt<C>(wy, c * ns + idx, out[c]);
+                }
+                lds[Lay::addr(0, 4 * line + c, idx)] = out[c];
+            }
+        }
+        // one site's operands live at a time (the next site's loads are not
+        // hoisted above this one's stores)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    // ---- forward x transform of the next stage's input, own component
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[0][m] = lds[Lay::addr(0, cl, t + T * m)];
+    fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, cl, tw);
+    if (act) {
+        gptr<nv2<R>> p = wview<R>(S->buf[BUF_T]) + base + q * ns + t;
+#pragma unroll
+        for (int m = 0; m < E; ++m) gstore_nt<C>(p, T * m, v[0][m]);
+    }
+}
+
 // ------------------------------------------------------------------ column pass
 template <class R, int N, int V, int MODE, int AXIS>
 __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArgs a) {
@@ -737,7 +955,8 @@ __global__ void __launch_bounds__((LineVar<R, N, WIDE>::T)) line_kernel(PassArgs
 struct RowVariant { const void* stage[4]; int threads, rows; size_t lds; };
 struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
-    int nvar;
+    int nvar;                      // row-pass variants
+    int nvar_col;                  // column-pass variants
     RowVariant row[NVAR];          // the RK4 stage pass, by variant
     const void* row_other[ROW_NMODES];  // other row modes (variant 0)
     int row0_threads, row0_rows;
@@ -754,6 +973,13 @@ RowVariant make_row_variant() {
     using VC = RowVar<R, N, V>;
     return RowVariant{{(const void*)row_kernel<R, N, V, ROW_STAGE, 0>, (const void*)row_kernel<R, N, V, ROW_STAGE, 1>,
                        (const void*)row_kernel<R, N, V, ROW_STAGE, 2>, (const void*)row_kernel<R, N, V, ROW_STAGE, 3>},
+                      VC::THREADS, VC::ROWS, VC::BYTES};
+}
+template <class R, int N, int V>
+RowVariant make_row_cs_variant() {
+    using VC = RowCsVar<R, N, V>;
+    return RowVariant{{(const void*)row_cs_kernel<R, N, V, 0>, (const void*)row_cs_kernel<R, N, V, 1>,
+                       (const void*)row_cs_kernel<R, N, V, 2>, (const void*)row_cs_kernel<R, N, V, 3>},
                       VC::THREADS, VC::ROWS, VC::BYTES};
 }
 template <class R, int N, int V>
@@ -776,15 +1002,20 @@ template <class R, int N>
 SizeKernels make_size_kernels() {
     SizeKernels k;
     k.nvar = nvar<N>();
+    k.nvar_col = nvar_col<N>();
     k.row[0] = make_row_variant<R, N, 0>();
     k.col[0] = make_col_variant<R, N, 0>();
     if constexpr (nvar<N>() > 1) {
         k.row[1] = make_row_variant<R, N, 1>();
         k.row[2] = make_row_variant<R, N, 2>();
         k.row[3] = make_row_variant<R, N, 3>();
+        k.row[4] = make_row_cs_variant<R, N, 4>();
+        k.row[5] = make_row_cs_variant<R, N, 5>();
         k.col[1] = make_col_variant<R, N, 1>();
         k.col[2] = make_col_variant<R, N, 2>();
         k.col[3] = make_col_variant<R, N, 3>();
+        k.col[4] = k.col[2];
+        k.col[5] = k.col[3];
     } else {
         for (int v = 1; v < NVAR; ++v) {
             k.row[v] = k.row[0];
