@@ -163,10 +163,13 @@ struct Group {
     int grid;
     std::vector<int> solves;
     const swf::SizeKernels* k[3] = {nullptr, nullptr, nullptr};
-    // offsets (int2) into the item array and counts, per tile variant
+    // offsets (int2) into the item array and counts: the stepping passes per
+    // tile variant, then the whole-state row and column kernels
     size_t it_row[swf::NVAR] = {}, it_coly[swf::NVAR] = {}, it_colz[swf::NVAR] = {};
     int n_row[swf::NVAR] = {}, n_coly[swf::NVAR] = {}, n_colz[swf::NVAR] = {};
-    int vr = 0, vy = 0, vz = 0;   // tile variants in use
+    size_t it_orow = 0, it_ocy = 0, it_ocz = 0;
+    int n_orow = 0, n_ocy = 0, n_ocz = 0;
+    int vr = 0, vy = 0, vz = 0;   // tile variants of the stepping passes in use
 };
 
 struct Plan {
@@ -217,35 +220,42 @@ static void xcd_group_order(std::vector<int2>& items, size_t first, int G) {
         for (size_t j = 0; j < span; ++j) items[first + i + (j % G) * 8 + j / G] = tmp[i + j];
 }
 
+// Work items (solve, tile) of a row pass with `rows` lines per block, or of a
+// column pass along `axis` with `w` columns per block; returns the offset.
+static size_t row_items(Plan& P, const Group& g, int rows, int& count) {
+    const swf_grid& G = P.grids[g.grid];
+    const int n1 = G.dim >= 2 ? G.n[1] : 1, n2 = G.dim >= 3 ? G.n[2] : 1;
+    const size_t first = P.items.size();
+    for (int s : g.solves)
+        for (int tile = 0; tile < (n1 * n2 + rows - 1) / rows; ++tile) P.items.push_back(make_int2(s, tile));
+    count = (int)(P.items.size() - first);
+    return first;
+}
+static size_t col_items(Plan& P, const Group& g, int axis, int w, int& count) {
+    const swf_grid& G = P.grids[g.grid];
+    const int n0 = G.n[0], other = axis == 1 ? (G.dim >= 3 ? G.n[2] : 1) : G.n[1];
+    const size_t first = P.items.size();
+    const int ntx = (n0 + w - 1) / w;
+    for (int s : g.solves)
+        for (int tile = 0; tile < ntx * other; ++tile) P.items.push_back(make_int2(s, tile));
+    count = (int)(P.items.size() - first);
+    xcd_group_order(P.items, first, std::max(1, 128 / (w * (int)P.csize)));
+    return first;
+}
+
 static void add_items(Plan& P, Group& g, int fp64) {
     const swf_grid& G = P.grids[g.grid];
-    const int n0 = G.n[0], n1 = G.dim >= 2 ? G.n[1] : 1, n2 = G.dim >= 3 ? G.n[2] : 1;
-    g.k[0] = swf::size_kernels(fp64, n0);
-    if (G.dim >= 2) g.k[1] = swf::size_kernels(fp64, n1);
-    if (G.dim >= 3) g.k[2] = swf::size_kernels(fp64, n2);
+    g.k[0] = swf::size_kernels(fp64, G.n[0]);
+    if (G.dim >= 2) g.k[1] = swf::size_kernels(fp64, G.n[1]);
+    if (G.dim >= 3) g.k[2] = swf::size_kernels(fp64, G.n[2]);
     for (int v = 0; v < swf::NVAR; ++v) {
-        g.it_row[v] = P.items.size();
-        const int rows = g.k[0]->row[v].rows;
-        for (int s : g.solves)
-            for (int tile = 0; tile < (n1 * n2 + rows - 1) / rows; ++tile) P.items.push_back(make_int2(s, tile));
-        g.n_row[v] = (int)(P.items.size() - g.it_row[v]);
-        if (G.dim >= 2) {
-            g.it_coly[v] = P.items.size();
-            const int ntx = (n0 + g.k[1]->col[v].w - 1) / g.k[1]->col[v].w;
-            for (int s : g.solves)
-                for (int tile = 0; tile < ntx * n2; ++tile) P.items.push_back(make_int2(s, tile));
-            g.n_coly[v] = (int)(P.items.size() - g.it_coly[v]);
-            xcd_group_order(P.items, g.it_coly[v], std::max(1, 128 / (g.k[1]->col[v].w * (int)P.csize)));
-        }
-        if (G.dim >= 3) {
-            g.it_colz[v] = P.items.size();
-            const int ntx = (n0 + g.k[2]->col[v].w - 1) / g.k[2]->col[v].w;
-            for (int s : g.solves)
-                for (int tile = 0; tile < ntx * n1; ++tile) P.items.push_back(make_int2(s, tile));
-            g.n_colz[v] = (int)(P.items.size() - g.it_colz[v]);
-            xcd_group_order(P.items, g.it_colz[v], std::max(1, 128 / (g.k[2]->col[v].w * (int)P.csize)));
-        }
+        g.it_row[v] = row_items(P, g, g.k[0]->row[v].rows, g.n_row[v]);
+        if (G.dim >= 2) g.it_coly[v] = col_items(P, g, 1, g.k[1]->cd[v].w, g.n_coly[v]);
+        if (G.dim >= 3) g.it_colz[v] = col_items(P, g, 2, g.k[2]->cd[v].w, g.n_colz[v]);
     }
+    g.it_orow = row_items(P, g, g.k[0]->row0_rows, g.n_orow);
+    if (G.dim >= 2) g.it_ocy = col_items(P, g, 1, g.k[1]->col.w, g.n_ocy);
+    if (G.dim >= 3) g.it_ocz = col_items(P, g, 2, g.k[2]->col.w, g.n_ocz);
 }
 
 static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_grids, const swf_term* terms,
@@ -543,7 +553,6 @@ struct swf_ctx {
     char* arena = nullptr;
     bool own_arena = false;
     int step = 0;
-    bool t_valid = true;
     size_t lds_max = 65536;       // dynamic LDS one workgroup may use on this device
     void* pm_buf = nullptr;       // pair-matrix scratch (grown on demand, freed by swf_free)
     size_t pm_bytes = 0;
@@ -656,7 +665,7 @@ static double group_sites(swf_ctx* ctx, const Group& g) {
 
 // Launch one pass kernel over n items starting at item offset `it`.
 static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threads, size_t lds, swf::PassArgs a,
-                  int kind, double bytes) {
+                  int kind, double bytes, int gy = 1) {
     if (nitems <= 0) return SWF_OK;
     a.items = ctx->d_items() + it;
     a.nitems = nitems;
@@ -670,7 +679,7 @@ static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threa
         if (r) return r;
         HIPCHK(hipEventRecord(e0, ctx->st));
     }
-    HIPCHK(hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, ctx->st));
+    HIPCHK(hipLaunchKernel(fn, dim3(blocks, gy), dim3(threads), args, lds, ctx->st));
     if (prof) {
         HIPCHK(hipEventRecord(e1, ctx->st));
         ctx->pending.push_back({e0, e1, kind, bytes});
@@ -678,7 +687,7 @@ static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threa
     return SWF_OK;
 }
 
-// x-axis pass of a group in the given mode.
+// x-axis pass of a group in the given mode (ROW_STAGE: the RK4 stage pass).
 static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, int dst, double tex, long long ph2,
                     int kind = 4) {
     const auto* k = g.k[0];
@@ -690,38 +699,70 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     a.ph2 = ph2;
     a.h0row = ctx->P.grids[g.grid].dim == 1 ? 1 : 0;
     double trav = 2;
-    if (mode == swf::ROW_STAGE) trav = stage == 0 ? 4 : (stage == 1 ? 6 : 5);
-    else if (mode == swf::ROW_RHS) trav = 3;
+    if (mode == swf::ROW_STAGE) {
+        // stage input, the G buffer (2D, 3D), the RK4 operand and outputs
+        static const double tr[4] = {2, 4, 3, 3};
+        trav = tr[stage] + (ctx->P.grids[g.grid].dim >= 2 ? 1 : 0);
+    } else if (mode == swf::ROW_RHS) {
+        trav = 3;
+    }
     const double bytes = trav * 4.0 * ctx->P.csize * group_sites(ctx, g);
     if (mode == swf::ROW_STAGE) {
         const auto& v = k->row[g.vr];
         return launch(ctx, v.stage[stage], g.n_row[g.vr], g.it_row[g.vr], v.threads, v.lds, a, kind, bytes);
     }
-    return launch(ctx, k->row_other[mode], g.n_row[0], g.it_row[0], k->row0_threads, k->row0_lds, a, kind, bytes);
+    return launch(ctx, k->row_other[mode], g.n_orow, g.it_orow, k->row0_threads, k->row0_lds, a, kind, bytes);
 }
 
+// Whole-state column transform of a group along `axis` (in place on `role`).
 static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, int kind = 4) {
-    const int v = axis == 1 ? g.vy : g.vz;
-    const auto& cv = g.k[axis]->col[v];
+    const auto& cv = g.k[axis]->col;
     swf::PassArgs a = pass_args(ctx);
     a.dst = role;
     a.src = role;
-    const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
-    const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
+    const int n = axis == 1 ? g.n_ocy : g.n_ocz;
+    const size_t it = axis == 1 ? g.it_ocy : g.it_ocz;
     return launch(ctx, cv.fn[axis - 1][mode], n, it, cv.threads, cv.lds, a, kind,
                   2.0 * 4.0 * ctx->P.csize * group_sites(ctx, g));
 }
 
-// k-space kinetic pass of a group (between the forward x pass and the row epilogue).
-static int kinetic_cols(swf_ctx* ctx, const Group& g, int role, bool stepping) {
+// Stepping column pass along `axis` of the stage input `src`: alpha^j D_j of
+// every component into the G buffer (written for y, added for z).
+static int cd_pass(swf_ctx* ctx, const Group& g, int axis, int src, int kind) {
+    const int v = axis == 1 ? g.vy : g.vz;
+    const auto& cv = g.k[axis]->cd[v];
+    const int accum = axis == 2 ? 1 : 0;
+    swf::PassArgs a = pass_args(ctx);
+    a.src = src;
+    a.dst = swf::BUF_T;
+    const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
+    const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
+    return launch(ctx, cv.fn[axis - 1][accum], n, it, cv.threads, cv.lds, a, kind,
+                  (2.0 + accum) * 4.0 * ctx->P.csize * group_sites(ctx, g), 4);
+}
+
+// The passes of one RK4 stage of a group: the column derivatives of the stage
+// input, then the row pass.
+static int stage_passes(swf_ctx* ctx, const Group& g, int s) {
     const int dim = ctx->P.grids[g.grid].dim;
-    const int ky = stepping ? 1 : 4, kz = stepping ? 2 : 4;
+    const int src = s == 0 ? swf::BUF_Y : swf::BUF_YS;
     int r = SWF_OK;
-    if (dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, role, ky);
+    if (dim >= 2) r = cd_pass(ctx, g, 1, src, 1);
+    if (!r && dim >= 3) r = cd_pass(ctx, g, 2, src, 2);
+    if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0, 0);
+    return r;
+}
+
+// k-space kinetic term of a whole state that the forward x pass left in
+// `role` (operator test hook): column transforms with -i H0 / N on the last axis.
+static int kinetic_cols(swf_ctx* ctx, const Group& g, int role) {
+    const int dim = ctx->P.grids[g.grid].dim;
+    int r = SWF_OK;
+    if (dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, role);
     if (dim == 3) {
-        r = col_pass(ctx, g, 1, swf::COL_FWD, role, ky);
-        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, role, kz);
-        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, role, ky);
+        r = col_pass(ctx, g, 1, swf::COL_FWD, role);
+        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, role);
+        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, role);
     }
     return r;
 }
@@ -844,25 +885,13 @@ static int bw2_accum(swf_ctx* ctx) {
     return SWF_OK;
 }
 
-// Forward x pass Y -> T for every solve (after the state was set from the host).
-static int refresh_T(swf_ctx* ctx) {
-    if (ctx->t_valid) return SWF_OK;
-    for (const auto& g : groups(ctx)) {
-        int r = row_pass(ctx, g, swf::ROW_FWD, 0, swf::BUF_Y, swf::BUF_T, 0, 0);
-        if (r) return r;
-    }
-    ctx->t_valid = true;
-    return SWF_OK;
-}
-
 // Enqueue one full RK4 step of every solve.
 static int enqueue_step(swf_ctx* ctx) {
     if (ctx->opt.batched && ctx->opt.chunk > 0 && ctx->P.hv.empty()) {
         // chunk-major: all four stages of one chunk before the next chunk
         for (const auto& g : groups(ctx))
             for (int s = 0; s < 4; ++s) {
-                int r = kinetic_cols(ctx, g, swf::BUF_T, true);
-                if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0, 0);
+                int r = stage_passes(ctx, g, s);
                 if (r) return r;
             }
         HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
@@ -873,8 +902,7 @@ static int enqueue_step(swf_ctx* ctx) {
         if (!r && ctx->P.bw2) r = bw2_stage(ctx, s);
         if (r) return r;
         for (const auto& g : groups(ctx)) {
-            r = kinetic_cols(ctx, g, swf::BUF_T, true);
-            if (!r) r = row_pass(ctx, g, swf::ROW_STAGE, s, 0, 0, 0, 0, 0);
+            r = stage_passes(ctx, g, s);
             if (r) return r;
         }
     }
@@ -935,7 +963,6 @@ static int line_steps(swf_ctx* ctx, int n) {
         HIPCHK(swf::launch_advance(ctx->d_step(), c, ctx->st));
         done += c;
     }
-    ctx->t_valid = false;   // the FFT buffer no longer holds the transform of Y
     return SWF_OK;
 }
 
@@ -961,7 +988,7 @@ static int build_graph(swf_ctx* ctx) {
 static std::string tune_key(swf_ctx* ctx, const Group& g) {
     const swf_grid& G = ctx->P.grids[g.grid];
     char b[160];
-    snprintf(b, sizeof(b), "%s d%d n%dx%dx%d b%zu", ctx->P.fp64 ? "f64" : "f32", G.dim, G.n[0], G.n[1], G.n[2],
+    snprintf(b, sizeof(b), "deriv %s d%d n%dx%dx%d b%zu", ctx->P.fp64 ? "f64" : "f32", G.dim, G.n[0], G.n[1], G.n[2],
              g.solves.size());
     return b;
 }
@@ -1008,8 +1035,8 @@ static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
         const int dim = ctx->P.grids[g.grid].dim;
         if (it != cache.end()) {
             g.vr = std::min(it->second[0], g.k[0]->nvar - 1);
-            g.vy = dim >= 2 ? std::min(it->second[1], g.k[1]->nvar_col - 1) : 0;
-            g.vz = dim >= 3 ? std::min(it->second[2], g.k[2]->nvar_col - 1) : 0;
+            g.vy = dim >= 2 ? std::min(it->second[1], g.k[1]->nvar - 1) : 0;
+            g.vz = dim >= 3 ? std::min(it->second[2], g.k[2]->nvar - 1) : 0;
             rep << key << ": cached " << g.vr << " " << g.vy << " " << g.vz << "\n";
             continue;
         }
@@ -1026,13 +1053,12 @@ static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
         }
         g.vr = bv;
         for (int axis = 1; axis < dim; ++axis) {
-            const int mode = (axis == dim - 1) ? swf::COL_H0 : swf::COL_FWD;
             best = 1e30f;
             bv = 0;
-            for (int v = 0; v < g.k[axis]->nvar_col; ++v) {
+            for (int v = 0; v < g.k[axis]->nvar; ++v) {
                 (axis == 1 ? g.vy : g.vz) = v;
                 float ms = 0;
-                int r = time_it(ctx, [&] { return col_pass(ctx, g, axis, mode, swf::BUF_T, 4); }, reps, &ms);
+                int r = time_it(ctx, [&] { return cd_pass(ctx, g, axis, swf::BUF_YS, 4); }, reps, &ms);
                 if (r) { ctx->opt.profile = prof; return r; }
                 rep << key << ": col" << axis << " v" << v << " " << ms << " ms\n";
                 if (ms < best) { best = ms; bv = v; }
@@ -1085,7 +1111,6 @@ static int kspace(swf_ctx* ctx, int s) {
     if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_T);
     if (r) return r;
     ctx->kvalid[s] = 1;
-    ctx->t_valid = false;
     return SWF_OK;
 }
 
@@ -1322,7 +1347,6 @@ static int bw_terms(swf_ctx* ctx, int v) {
         if (!r && dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_ACC);
         if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_ACC);
         if (r) return r;
-        ctx->t_valid = false;
     }
     swf::RedArgs a;
     memset(&a, 0, sizeof(a));
@@ -1508,7 +1532,11 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 const auto* k = g.k[ax];
                 if (!k) continue;
                 for (int m = 0; m < swf::ROW_NMODES; ++m)
-                    INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
+                    if (k->row_other[m])
+                        INITCHK(hipFuncSetAttribute(k->row_other[m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row0_lds));
+                for (int a = 0; a < 2; ++a)
+                    for (int m = 0; m < 3; ++m)
+                        INITCHK(hipFuncSetAttribute(k->col.fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col.lds));
                 if (k->line[0] && ax == 0)
                     for (int w = 0; w < 2; ++w)
                         INITCHK(hipFuncSetAttribute(k->line[w], hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1518,8 +1546,8 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                     for (int st = 0; st < 4; ++st)
                         INITCHK(hipFuncSetAttribute(k->row[v].stage[st], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
                     for (int a = 0; a < 2; ++a)
-                        for (int m = 0; m < 3; ++m)
-                            INITCHK(hipFuncSetAttribute(k->col[v].fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->col[v].lds));
+                        for (int m = 0; m < 2; ++m)
+                            INITCHK(hipFuncSetAttribute(k->cd[v].fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->cd[v].lds));
                 }
             }
     ctx->kvalid.assign(P.solves.size(), 0);
@@ -1530,8 +1558,8 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         for (auto* gl : {&P.batched, &P.single})
             for (auto& g : *gl) {
                 g.vr = std::min(v, g.k[0]->nvar - 1);
-                g.vy = g.k[1] ? std::min(v, g.k[1]->nvar_col - 1) : 0;
-                g.vz = g.k[2] ? std::min(v, g.k[2]->nvar_col - 1) : 0;
+                g.vy = g.k[1] ? std::min(v, g.k[1]->nvar - 1) : 0;
+                g.vz = g.k[2] ? std::min(v, g.k[2]->nvar - 1) : 0;
             }
     } else if (opt->tune && !line_path(ctx)) {
         int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
@@ -1577,8 +1605,6 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
             if (K > 0 && (ctx->step + done) % K == 0 && (r = check(ctx->step + done))) return (swf_status)r;
         }
     } else {
-        r = refresh_T(ctx);
-        if (r) return (swf_status)r;
         for (int i = 0; i < n_steps; ++i) {
             if (ctx->gexec) {
                 HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
@@ -1622,7 +1648,6 @@ swf_status swf_reset(swf_ctx* ctx) {
     HIPCHK(hipMemsetAsync(ctx->d_M(), 0, sizeof(double2) * 3 * std::max<size_t>(1, ctx->P.hv.size()), ctx->st));
     if (ctx->P.bw2) HIPCHK(hipMemsetAsync(ctx->d_M2(), 0, sizeof(double2) * 3 * ctx->P.hv.size(), ctx->st));
     ctx->step = 0;
-    ctx->t_valid = true;
     std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
     std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
     r = leave(ctx);
@@ -1869,7 +1894,6 @@ swf_status swf_set_psi(swf_ctx* ctx, int i, const double* host, int step_index) 
     ctx->step = step_index;
     HIPCHK(hipMemcpyAsync(ctx->d_step(), &step_index, sizeof(int), hipMemcpyHostToDevice, ctx->st));
     HIPCHK(hipStreamSynchronize(ctx->st));
-    ctx->t_valid = false;
     std::fill(ctx->kvalid.begin(), ctx->kvalid.end(), 0);
     std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
     return SWF_OK;
@@ -1922,12 +1946,11 @@ swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in,
         if (dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_T);
         if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_T);
     } else {
-        r = kinetic_cols(ctx, g, swf::BUF_T, false);
+        r = kinetic_cols(ctx, g, swf::BUF_T);
         if (!r) r = row_pass(ctx, g, op == 1 ? swf::ROW_INV : swf::ROW_RHS, 0, swf::BUF_YS, swf::BUF_ACC, t, 0);
         role_out = swf::BUF_ACC;
     }
     if (r) return (swf_status)r;
-    ctx->t_valid = false;
     ctx->kvalid[i] = 0;
     std::fill(ctx->bw_done.begin(), ctx->bw_done.end(), 0);
     return copy_state(ctx, i, role_out, out, true);

@@ -4,13 +4,25 @@
 // One RK4 stage of the scattered-wave equation (eq. (scatDirac) of arXiv
 // 2512.16889 multiplied by gamma^0),
 //     k = IFFT[-i H0(k) FFT y_i] - i (A_0 + alpha^j A_j)(t_i) (y_i + psi_b(t_i)),
-// is split into passes over the spinor-of-arrays state:
-//   * column passes (axes y, z): forward transform, and on the last
-//     non-trivial axis the -i H0(k)/N multiply and the inverse transform;
-//   * one row pass (axis x): inverse transform, the stage epilogue (source
-//     term, RK4 accumulation, absorber) and the forward x transform of the
-//     next stage's input, so each stage costs one read and one write of the
-//     FFT buffer per pass plus the RK4 state traffic.
+// H0(k) = alpha.k + beta.  Spectral derivatives along different axes commute,
+// so the kinetic term is a sum over axes,
+//     IFFT[-i H0 FFT y] = -i sum_j alpha^j D_j y - i beta y,
+//     D_j y = IFFT_j[k_j FFT_j y]   (a one-dimensional transform along axis j),
+// and in the Dirac representation every alpha^j is a signed permutation of
+// the four components: (alpha^1 y)_q = y_{3-q}, (alpha^2 y)_q = -+i y_{3-q}
+// (- for even q), (alpha^3 y)_q = +-y_{q^2} (+ for q = 0, 2).  A stage is
+// therefore split into passes over the spinor-of-arrays state that never mix
+// components inside a transform:
+//   * column passes (axes y, z): one component per block; D_j of the component
+//     alpha^j takes, written (y) or added (z) into the G buffer at the
+//     component it lands on, G = alpha^2 D_y y + alpha^3 D_z y;
+//   * one row pass (axis x): D_x of the component alpha^1 takes, then the
+//     stage epilogue (beta and trivial-axis terms, the source, the RK4
+//     update, the absorber) for the thread's own component.
+// Per RK4 step this reads and writes 36 state arrays in 3D (24 in 2D, 12 in
+// 1D).  The other row and column kernels (forward / inverse transforms of a
+// whole state, the full right-hand side) serve the t_in observables, the
+// operator test hook and the Breit-Wheeler partial-integration route.
 #pragma once
 #include "swf_dev.h"
 
@@ -59,29 +71,23 @@ template <int N> constexpr int half_t() {
     constexpr int T = FftPlan<N>::T;
     return (T % 2 == 0 && 2 * N / T <= 16 && plan_ok<N, T / 2>()) ? T / 2 : T;
 }
-constexpr int NVAR = 6;       // row-pass variants (4, 5: component-split)
-constexpr int NVAR_COL = 4;   // column-pass variants
+constexpr int NVAR = 4;       // tile variants of the stepping passes (row and column)
 template <int N> constexpr int nvar() { return N >= 256 ? NVAR : 1; }
-template <int N> constexpr int nvar_col() { return N >= 256 ? NVAR_COL : 1; }
 constexpr size_t LDS_CAP = 72 * 1024;
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int cg_fit(size_t per_comp) { return 4 * per_comp <= LDS_CAP ? 4 : (2 * per_comp <= LDS_CAP ? 2 : 1); }
 
-// waves per SIMD the compiler is asked to fit (0: no hint)
+// Tile of the row kernel (whole-state transforms and right-hand side): the
+// default plan, T threads per x-line, up to 256 threads per block.
 template <class R, int N, int V> struct RowVar {
-    // v3: the few-points-per-thread plan; for the mixed-radix lengths v2 too,
-    // with the stage epilogue streamed point by point (STREAM: fewer live
-    // registers where the classic epilogue spills)
-    static constexpr bool SMALL = (V == 3 && has_small_plan<N>()) || (V == 2 && has_plans<N>());
-    static constexpr bool STREAM = V == 2 && has_plans<N>();
-    using PL = typename PlanSel<N, SMALL>::type;
+    using PL = FftPlan<N>;
     static constexpr int T = PL::T;
-    static constexpr int ROWS = imax(1, (V == 2 ? 128 : 256) / T);
+    static constexpr int ROWS = imax(1, 256 / T);
     static constexpr int THREADS = T * ROWS;
     using Lay = RowLay<N, ROWS>;
     static constexpr size_t PER_COMP = (size_t)ROWS * Lay::STRIDE * sizeof(cpx<R>);
-    static constexpr int CG = V == 0 ? 1 : cg_fit(PER_COMP);
+    static constexpr int CG = 1;
     static constexpr size_t BYTES = CG * PER_COMP;
     static constexpr bool SEQ = false;
     static_assert(plan_ok<N, T, PL>(), "row variant violates the FFT plan constraints");
@@ -262,11 +268,8 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
             double ts;
             if constexpr (MODE == ROW_RHS) {
                 ts = a.t_explicit;
-            } else if constexpr (MODE == ROW_SRC) {
-                const double cst = a.stage == 0 ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
-                ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
             } else {
-                constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
+                const double cst = a.stage == 0 ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
                 ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
             }
             const int nterm = S->nterm;
@@ -286,81 +289,10 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
                 sh_wc[q] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
             }
             if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
-            if constexpr (VC::STREAM && MODE == ROW_STAGE) {
-                // point by point: the stage input, the RK4 operands and the
-                // outputs of one point are loaded, combined and stored before
-                // the next, so only the transform array stays live
-                __syncthreads();
-                const R h = (R)(-a.dt);
-                const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0), third = (R)(1.0 / 3.0);
-                const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
-                const C phyz = sh_phyz[line];
-                const long long mask = S->mask;
-                const R myz = mask >= 0 ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
-                gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base + t;
-                gptr<const nv2<R>> py = cview<R>(S->buf[BUF_Y]) + base + t;
-                gptr<const nv2<R>> pacc = cview<R>(S->buf[BUF_ACC]) + base + t;
-                gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base + t;
-                gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base + t;
-                gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base + t;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    R A[4] = {(R)0, (R)0, (R)0, (R)0};
-#pragma unroll
-                    for (int j = 0; j < MAX_TERMS; ++j) {
-                        if (j < nterm) {
-                            const R f = sh_fyz[line][j] * rtab[sh_tab[j] + t + T * m];
-                            const int mu = sh_mu[j];
-                            A[0] += mu == 0 ? f : (R)0;
-                            A[1] += mu == 1 ? f : (R)0;
-                            A[2] += mu == 2 ? f : (R)0;
-                            A[3] += mu == 3 ? f : (R)0;
-                        }
-                    }
-                    const C ph = cmul(gload<C>(ctab, S->ph + t + T * m), phyz);
-                    const long long o = (long long)T * m;
-                    C yi[4], sv[4], vs[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        yi[q] = gload<C>(pin, q * ns + o);
-                        sv[q] = cadd(yi[q], cmul(wc[q], ph));
-                    }
-                    apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
-                    const R mk = (STAGE == 3 && mask >= 0) ? rtab[mask + t + T * m] * myz : (R)1;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const C k = cadd(v[q][m], cmul_mi(vs[q]));
-                        C out;
-                        if constexpr (STAGE == 0) {
-                            out = cadd(yi[q], cscale(k, h2));                                   // y_2
-                            if (act) gstore<C>(wys, q * ns + o, out);
-                        } else if constexpr (STAGE == 1) {
-                            const C y0 = gload<C>(py, q * ns + o);
-                            out = cadd(y0, cscale(k, h2));                                      // y_3
-                            const C acc = cscale(csub(cadd(yi[q], cscale(out, (R)2)), y0), third);
-                            if (act) {
-                                gstore<C>(wacc, q * ns + o, acc);
-                                gstore<C>(wys, q * ns + o, out);
-                            }
-                        } else if constexpr (STAGE == 2) {
-                            const C y0 = gload<C>(py, q * ns + o);
-                            out = cadd(y0, cscale(k, h));                                       // y_4
-                            if (act) gstore<C>(wys, q * ns + o, out);
-                        } else {
-                            const C acc = gload<C>(pacc, q * ns + o);
-                            out = cscale(cadd(cadd(acc, cscale(yi[q], third)), cscale(k, h6)), mk);
-                            if (act) gstore<C>(wy, q * ns + o, out);
-                        }
-                        v[q][m] = out;
-                    }
-                    // keep the scheduler from hoisting the next point's loads
-                    // above this one (that would bring back the whole arrays)
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            } else {
+            {
                 // state loads are independent of the barrier below: issue them first
                 C yi[4][E];
-                load((MODE == ROW_RHS || MODE == ROW_SRC) ? a.src : (STAGE == 0 ? BUF_Y : BUF_YS), yi);
+                load(a.src, yi);
                 __syncthreads();
                 // field A_mu on this line's points
                 R A[4][E];
@@ -397,290 +329,9 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
 #pragma unroll
                     for (int q = 0; q < 4; ++q) v[q][m] = cadd(v[q][m], cmul_mi(vs[q]));   // v = k
                 }
-                if constexpr (MODE == ROW_RHS || MODE == ROW_SRC) {
-                    store(a.dst, v);
-                    return;
-                } else {
-                    const R h = (R)(-a.dt);
-                    const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0);
-                    // Classical RK4 with the accumulator written once: with the stage
-                    // inputs y_2 = y + h/2 k1, y_3 = y + h/2 k2, y_4 = y + h k3,
-                    //   y_{n+1} = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
-                    //           = (y_2 + 2 y_3 - y)/3 + y_4/3 + h/6 k4,
-                    // so stage 1 stores acc = (y_2 + 2 y_3 - y)/3 and stage 3 finishes.
-                    if constexpr (STAGE == 0) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int m = 0; m < E; ++m) v[q][m] = cadd(yi[q][m], cscale(v[q][m], h2));   // y_2
-                        store(BUF_YS, v);
-                    } else if constexpr (STAGE == 1) {
-                        const R third = (R)(1.0 / 3.0);
-                        C y0[4][E], acc[4][E];
-                        load(BUF_Y, y0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int m = 0; m < E; ++m) {
-                                const C y3 = cadd(y0[q][m], cscale(v[q][m], h2));
-                                acc[q][m] = cscale(csub(cadd(yi[q][m], cscale(y3, (R)2)), y0[q][m]), third);
-                                v[q][m] = y3;
-                            }
-                        store(BUF_ACC, acc);
-                        store(BUF_YS, v);
-                    } else if constexpr (STAGE == 2) {
-                        C y0[4][E];
-                        load(BUF_Y, y0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int m = 0; m < E; ++m) v[q][m] = cadd(y0[q][m], cscale(v[q][m], h));   // y_4
-                        store(BUF_YS, v);
-                    } else {
-                        const R third = (R)(1.0 / 3.0);
-                        C acc[4][E];
-                        load(BUF_ACC, acc);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int m = 0; m < E; ++m)
-                                v[q][m] = cadd(cadd(acc[q][m], cscale(yi[q][m], third)), cscale(v[q][m], h6));
-                        const long long mask = S->mask;
-                        if (mask >= 0) {
-                            const R myz = rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz];
-#pragma unroll
-                            for (int m = 0; m < E; ++m) {
-                                const R mk = rtab[mask + t + T * m] * myz;
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) v[q][m] = cscale(v[q][m], mk);
-                            }
-                        }
-                        store(BUF_Y, v);
-                    }
-                }
-            }
-            if constexpr (MODE == ROW_STAGE) {
-                // forward x transform of the next stage's input
-                fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
-                store(BUF_T, v);
+                store(a.dst, v);
             }
         }
-    }
-}
-
-// ------------------------------------------------------------------ component-split row pass
-// The RK4 stage pass with one spinor component per thread.  T threads share
-// each component line (E = N/T points each), so a thread holds E points of
-// the transform instead of 4E and needs a quarter of the registers.  The
-// stage epilogue couples the four components of a site (A-slash mixes them):
-// after the inverse x transform every thread leaves its points in LDS, each
-// thread then finishes the sites t + T m, m = q, q+4, ... of its lane (all
-// four components of each), writes the next stage input back in place, and
-// after a barrier every thread reads its own component again and transforms
-// it forward.
-//   v4: the few-points-per-thread plan, 256 threads per block;
-//   v5: the default plan, 128 threads per block (fewer exchange steps).
-template <class R, int N, int V> struct RowCsVar {
-    static constexpr bool SMALL = V == 4 && has_small_plan<N>();
-    using PL = typename PlanSel<N, SMALL>::type;
-    static constexpr int T = PL::T;
-    static constexpr int E = N / T;
-    static constexpr int ROWS = imax(1, (V == 4 ? 256 : 128) / (4 * T));
-    static constexpr int THREADS = 4 * T * ROWS;
-    using Lay = RowLay<N, 4 * ROWS>;
-    static constexpr size_t BYTES = (size_t)4 * ROWS * Lay::STRIDE * sizeof(cpx<R>);
-    // waves per SIMD the LDS of a compute unit (160 KiB) allows; the compiler
-    // is asked to fit that many (at most 4) in the register file
-    static constexpr int BLOCKS_PER_CU = (int)(163840 / (BYTES + N * sizeof(cpx<R>) + 512));
-    static constexpr int WAVES = imax(1, imin(4, BLOCKS_PER_CU * (THREADS / 64) / 4));
-    static_assert(plan_ok<N, T, PL>(), "component-split row variant violates the FFT plan constraints");
-    static_assert(THREADS <= 1024, "component-split row block too large");
-};
-
-template <class R, int N, int V, int STAGE>
-__global__ void __launch_bounds__((RowCsVar<R, N, V>::THREADS))
-__attribute__((amdgpu_waves_per_eu(RowCsVar<R, N, V>::WAVES, 8))) row_cs_kernel(PassArgs a) {
-    using C = cpx<R>;
-    using VC = RowCsVar<R, N, V>;
-    constexpr int T = VC::T;
-    constexpr int E = VC::E;
-    constexpr int ROWS = VC::ROWS;
-    using Lay = typename VC::Lay;
-    using PL = typename VC::PL;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* lds = reinterpret_cast<C*>(smem_raw);
-    __shared__ R sh_fyz[ROWS][MAX_TERMS];
-    __shared__ int sh_mu[MAX_TERMS];
-    __shared__ long long sh_tab[MAX_TERMS];
-    __shared__ C sh_wc[4];
-    __shared__ C sh_phyz[ROWS];
-    __shared__ C tw[N];
-
-    const int tid = threadIdx.x;
-    const int t = tid % T;
-    const int q = (tid / T) % 4;
-    const int line = tid / (4 * T);
-    const int cl = 4 * line + q;          // LDS line of this thread's component
-    const int2 it = a.items[blockIdx.x];
-    const SolveDev* __restrict__ S = a.solves + it.x;
-    const int row = it.y * ROWS + line;
-    const bool act = row < S->nrows;
-    const int rowc = act ? row : 0;
-    const long long base = (long long)rowc * N;
-    const long long ns = S->nsites;
-    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
-    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
-    // twiddles: first read after the first exchange's barriers
-    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[0] + i);
-    const int n0 = S->n[0], n1 = S->n[1];
-    const int yy = rowc % n1, zz = rowc / n1;
-
-    C v[1][E];
-    {
-        gptr<const nv2<R>> p = cview<R>(S->buf[BUF_T]) + base + q * ns + t;
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[0][m] = gload_nt<C>(p, T * m);
-    }
-    // per-line constants of the stage time, published by the transform's barriers
-    constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
-    const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
-    const int nterm = S->nterm;
-    if (q == 0) {
-        for (int j = t; j < nterm; j += T) {
-            const TermDev tm = a.terms[S->term0 + j];
-            const double coef = tm.amp * profile_t(tm.ft_type, tm.c, tm.w, tm.k, tm.phi, ts);
-            sh_fyz[line][j] = (R)coef * rtab[tm.tab + n0 + yy] * rtab[tm.tab + n0 + n1 + zz];
-            if (line == 0) {
-                sh_mu[j] = tm.mu;
-                sh_tab[j] = tm.tab;
-            }
-        }
-        if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
-    }
-    if (tid < 4) {
-        double sn, cs;
-        sincos(-S->E * ts, &sn, &cs);
-        const double wr = S->w[2 * tid], wi = S->w[2 * tid + 1];
-        sh_wc[tid] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
-    }
-    if (a.h0row) {
-        // one-dimensional grid: -i H0(k)/N couples the components of a mode, so
-        // the k-space line goes through LDS first (sites as in the epilogue)
-#pragma unroll
-        for (int m = 0; m < E; ++m) lds[Lay::addr(0, cl, t + T * m)] = v[0][m];
-        __syncthreads();
-        const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], sn = (R)S->inv_n;
-        const double dk = S->dk[0];
-#pragma unroll
-        for (int j = 0; j < (E + 3) / 4; ++j) {
-            const int m = q + 4 * j;
-            if (m < E) {
-                const int idx = t + T * m;
-                C w[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) w[c] = lds[Lay::addr(0, 4 * line + c, idx)];
-                apply_h0(w[0], w[1], w[2], w[3], (R)(dk * kindex(idx, N)), Ky, Kz, sn);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) lds[Lay::addr(0, 4 * line + c, idx)] = w[c];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[0][m] = lds[Lay::addr(0, cl, t + T * m)];
-    }
-    fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, cl, tw);
-    // the inverse transform into LDS, natural order
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < E; ++m) lds[Lay::addr(0, cl, t + T * m)] = v[0][m];
-    __syncthreads();
-
-    // ---- stage epilogue of the sites t + T m, m = q, q + 4, ...
-    const R h = (R)(-a.dt);
-    const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0), third = (R)(1.0 / 3.0);
-    const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
-    const C phyz = sh_phyz[line];
-    const long long mask = S->mask;
-    const R myz = (STAGE == 3 && mask >= 0) ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
-    gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base;
-    gptr<const nv2<R>> py = cview<R>(S->buf[BUF_Y]) + base;
-    gptr<const nv2<R>> pacc = cview<R>(S->buf[BUF_ACC]) + base;
-    gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base;
-    gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base;
-    gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base;
-#pragma unroll
-    for (int j = 0; j < (E + 3) / 4; ++j) {
-        const int m = q + 4 * j;
-        if (m < E) {
-            const int idx = t + T * m;
-            C yi[4], kin[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) yi[c] = gload_nt<C>(pin, c * ns + idx);
-            C y0[4];
-            if constexpr (STAGE == 1 || STAGE == 2) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) y0[c] = gload_nt<C>(py, c * ns + idx);
-            } else if constexpr (STAGE == 3) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) y0[c] = gload_nt<C>(pacc, c * ns + idx);
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) kin[c] = lds[Lay::addr(0, 4 * line + c, idx)];
-            R A[4] = {(R)0, (R)0, (R)0, (R)0};
-#pragma unroll
-            for (int jt = 0; jt < MAX_TERMS; ++jt) {
-                if (jt < nterm) {
-                    const R f = sh_fyz[line][jt] * rtab[sh_tab[jt] + idx];
-                    const int mu = sh_mu[jt];
-                    A[0] += mu == 0 ? f : (R)0;
-                    A[1] += mu == 1 ? f : (R)0;
-                    A[2] += mu == 2 ? f : (R)0;
-                    A[3] += mu == 3 ? f : (R)0;
-                }
-            }
-            const C ph = cmul(gload<C>(ctab, S->ph + idx), phyz);
-            C sv[4], vs[4], out[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) sv[c] = cadd(yi[c], cmul(wc[c], ph));
-            apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const C k = cadd(kin[c], cmul_mi(vs[c]));
-                // Classical RK4 with the accumulator written once (see row_kernel)
-                if constexpr (STAGE == 0) {
-                    out[c] = cadd(yi[c], cscale(k, h2));                                   // y_2
-                    if (act) gstore_nt<C>(wys, c * ns + idx, out[c]);
-                } else if constexpr (STAGE == 1) {
-                    out[c] = cadd(y0[c], cscale(k, h2));                                   // y_3
-                    const C acc = cscale(csub(cadd(yi[c], cscale(out[c], (R)2)), y0[c]), third);
-                    if (act) {
-                        gstore_nt<C>(wacc, c * ns + idx, acc);
-                        gstore_nt<C>(wys, c * ns + idx, out[c]);
-                    }
-                } else if constexpr (STAGE == 2) {
-                    out[c] = cadd(y0[c], cscale(k, h));                                    // y_4
-                    if (act) gstore_nt<C>(wys, c * ns + idx, out[c]);
-                } else {
-                    const R mk = mask >= 0 ? rtab[mask + idx] * myz : (R)1;
-                    out[c] = cscale(cadd(cadd(y0[c], cscale(yi[c], third)), cscale(k, h6)), mk);
-                    if (act) gstore_nt<C>(wy, c * ns + idx, out[c]);
-                }
-                lds[Lay::addr(0, 4 * line + c, idx)] = out[c];
-            }
-        }
-        // one site's operands live at a time (the next site's loads are not
-        // hoisted above this one's stores)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-    // ---- forward x transform of the next stage's input, own component
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[0][m] = lds[Lay::addr(0, cl, t + T * m)];
-    fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, cl, tw);
-    if (act) {
-        gptr<nv2<R>> p = wview<R>(S->buf[BUF_T]) + base + q * ns + t;
-#pragma unroll
-        for (int m = 0; m < E; ++m) gstore_nt<C>(p, T * m, v[0][m]);
     }
 }
 
@@ -751,6 +402,360 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore<C>(p, q * ns + (long long)(T * m) * stride, v[q][m]);
+    }
+}
+
+// ------------------------------------------------------------------ stepping passes
+// Source component and phase of the alpha^j entries (Dirac representation):
+// (alpha^1 y)_q = y_{3-q}; (alpha^2 y)_q = (-i for even q, +i for odd q) y_{3-q};
+// (alpha^3 y)_q = (+1 for q = 0, 2; -1 for q = 1, 3) y_{q^2}; beta = diag(1, 1, -1, -1).
+template <class C> __device__ __forceinline__ C alpha2_phase(int q, C v) { return (q & 1) ? cmul_i(v) : cmul_mi(v); }
+template <class C> __device__ __forceinline__ C alpha3_phase(int q, C v) { return (q & 1) ? cmake<C>(-v.x, -v.y) : v; }
+
+// Column derivative pass: the blocks of blockIdx.y = q transform the
+// component alpha^j takes for output component q along axis j = AXIS (y or
+// z), multiply by k_j / n_j, transform back, and write (ACCUM = 0) or add
+// (ACCUM = 1) the result, with alpha^j's phase, into component q of the G
+// buffer (a.dst).  a.src: the stage input.  One component per thread: E
+// points of the transform in registers.
+//   v0: default plan, one 128-byte line of x per tile;  v1: few-points plan, one line;
+//   v2: few-points plan, two lines;                      v3: default plan, two lines.
+template <class R, int N, int V> struct CdVar {
+    static constexpr int WANT = sizeof(R) == 4 ? 16 : 8;   // columns per 128-byte line
+    static constexpr bool SMALL = (V == 1 || V == 2) && has_small_plan<N>();
+    using PL = typename PlanSel<N, SMALL>::type;
+    static constexpr int T = PL::T;
+    static constexpr int E = N / T;
+    // widest power-of-two tile whose exchange buffer fits the LDS with the twiddles
+    static constexpr int WFIT = (int)((163840 - N * sizeof(cpx<R>) - 1024) / (N * sizeof(cpx<R>)));
+    static constexpr int WMAX = WFIT >= 32 ? 32 : (WFIT >= 16 ? 16 : (WFIT >= 8 ? 8 : (WFIT >= 4 ? 4 : 2)));
+    static constexpr int W = imax(1, imin(imin(WANT * (V >= 2 ? 2 : 1), 1024 / T), WMAX));
+    static constexpr int THREADS = T * W;
+    static constexpr size_t BYTES = (size_t)N * W * sizeof(cpx<R>);
+    static_assert(plan_ok<N, T, PL>(), "column derivative variant violates the FFT plan constraints");
+};
+
+template <class R, int N, int V, int AXIS, int ACCUM>
+__global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassArgs a) {
+    using C = cpx<R>;
+    using VC = CdVar<R, N, V>;
+    constexpr int T = VC::T;
+    constexpr int W = VC::W;
+    constexpr int E = VC::E;
+    using Lay = ColLay<N, W>;
+    using PL = typename VC::PL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    __shared__ C tw[N];
+
+    const int tid = threadIdx.x;
+    const int xl = tid % W;
+    const int t = tid / W;
+    const int q = blockIdx.y;                       // output component
+    const int src = AXIS == 1 ? 3 - q : (q ^ 2);    // the component alpha^j takes
+    // one tile = W adjacent columns of one solve at one fixed other-axis index
+    const int2 it = a.items[blockIdx.x];
+    const SolveDev* __restrict__ S = a.solves + it.x;
+    const int n0 = S->n[0], n1 = S->n[1];
+    const int ntx = (n0 + W - 1) / W;
+    const int other = it.y / ntx;
+    const int x = (it.y % ntx) * W + xl;
+    const bool act = x < n0;
+    const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
+    const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
+    const long long base = obase + (act ? x : 0) + (long long)t * stride;
+    const long long ns = S->nsites;
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[AXIS] + i);
+
+    C v[1][E];
+    C g[E];
+    {
+        gptr<const nv2<R>> p = cview<R>(S->buf[a.src]) + base + src * ns;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[0][m] = gload<C>(p, (long long)(T * m) * stride);
+        if constexpr (ACCUM) {
+            // the partial sum of the earlier axis, loaded ahead of the transforms
+            gptr<const nv2<R>> pg = cview<R>(S->buf[a.dst]) + base + q * ns;
+#pragma unroll
+            for (int m = 0; m < E; ++m) g[m] = gload<C>(pg, (long long)(T * m) * stride);
+        }
+    }
+    fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+    const double kscale = S->dk[AXIS] / (double)N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const C w = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
+        v[0][m] = AXIS == 1 ? alpha2_phase(q, w) : alpha3_phase(q, w);
+    }
+    fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+    if (act) {
+        gptr<nv2<R>> p = wview<R>(S->buf[a.dst]) + base + q * ns;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
+            gstore<C>(p, (long long)(T * m) * stride, o);
+        }
+    }
+}
+
+// Row (x) stage pass: the RK4 stage STAGE for one spinor component per
+// thread.  T threads share a component line (E = N/T points each), 4T a
+// grid line.  A thread reads its own component of the stage input y_i and
+// exchanges it through LDS for the two it also needs (3 - q and q ^ 2, the
+// partners alpha^j couples q to), transforms component 3 - q along x,
+// multiplies by k_x / n_0 and transforms back, which gives (alpha^1 D_x y)_q,
+// and then finishes its own component at its points:
+//     k_q = -i [alpha^1 D_x y + G + (beta y) + sum over trivial axes kappa_j (alpha^j y)
+//               + (A_0 + alpha^j A_j)(y + psi_b)]_q,
+// the RK4 update of component q with the accumulator written once, and the
+// absorber at the last stage.
+//   v0 / v1: few-points plan, 256 / 128 threads per block;
+//   v2 / v3 (SITE): few-points / default plan, 256 / 128 threads: the thread
+//   reads component 3 - q of the stage input for the transform straight from
+//   memory, leaves (alpha^1 D_x y)_q in LDS, and finishes whole sites (all
+//   four components of the sites t + T m, m = q, q+4, ...), reading the
+//   stage input there again, so the field and phase work is done once per site.
+template <class R, int N, int V> struct RdVar {
+    static constexpr bool SITE = V >= 2;
+    static constexpr bool SMALL = (V <= 2) && has_small_plan<N>();
+    using PL = typename PlanSel<N, SMALL>::type;
+    static constexpr int T = PL::T;
+    static constexpr int E = N / T;
+    static constexpr int ROWS = imax(1, ((V % 2) == 0 ? 256 : 128) / (4 * T));
+    static constexpr int THREADS = 4 * T * ROWS;
+    using Lay = RowLay<N, 4 * ROWS>;
+    static constexpr size_t BYTES = (size_t)4 * ROWS * Lay::STRIDE * sizeof(cpx<R>);
+    // waves per SIMD the compiler is asked to fit: what the LDS of a compute
+    // unit (160 KiB) allows, at most 2 in double (four components' worth of
+    // points stay live) and 4 in single precision
+    static constexpr int BLOCKS_PER_CU = (int)(163840 / (BYTES + N * sizeof(cpx<R>) + 512));
+    static constexpr int WAVES = imax(1, imin(SITE ? 4 : (sizeof(R) == 8 ? 2 : 4), BLOCKS_PER_CU * (THREADS / 64) / 4));
+    static_assert(plan_ok<N, T, PL>(), "row derivative variant violates the FFT plan constraints");
+    static_assert(THREADS <= 1024, "row derivative block too large");
+};
+
+template <class R, int N, int V, int STAGE>
+__global__ void __launch_bounds__((RdVar<R, N, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(PassArgs a) {
+    using C = cpx<R>;
+    using VC = RdVar<R, N, V>;
+    constexpr int T = VC::T;
+    constexpr int E = VC::E;
+    constexpr int ROWS = VC::ROWS;
+    using Lay = typename VC::Lay;
+    using PL = typename VC::PL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    __shared__ R sh_fyz[ROWS][MAX_TERMS];
+    __shared__ int sh_mu[MAX_TERMS];
+    __shared__ long long sh_tab[MAX_TERMS];
+    __shared__ C sh_wc[4];
+    __shared__ C sh_phyz[ROWS];
+    __shared__ C tw[N];
+
+    const int tid = threadIdx.x;
+    const int t = tid % T;
+    const int q = (tid / T) % 4;
+    const int line = tid / (4 * T);
+    const int qx = 3 - q, qz = q ^ 2;
+    const int2 it = a.items[blockIdx.x];
+    const SolveDev* __restrict__ S = a.solves + it.x;
+    const int row = it.y * ROWS + line;
+    const bool act = row < S->nrows;
+    const int rowc = act ? row : 0;
+    const long long base = (long long)rowc * N;
+    const long long ns = S->nsites;
+    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[0] + i);
+    const int n0 = S->n[0], n1 = S->n[1];
+    const int yy = rowc % n1, zz = rowc / n1;
+
+    gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base;
+    C v[1][E];
+    C yq[E], yx[E], yz[E];
+    if constexpr (VC::SITE) {
+        // the component alpha^1 takes, straight from memory (read again by the epilogue)
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[0][m] = gload<C>(pin, qx * ns + t + T * m);
+    } else {
+        // own component of the stage input
+#pragma unroll
+        for (int m = 0; m < E; ++m) yq[m] = gload_nt<C>(pin, q * ns + t + T * m);
+    }
+    // per-line constants of the stage time (read after the barriers below)
+    constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
+    const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+    const int nterm = S->nterm;
+    if (q == 0) {
+        for (int j = t; j < nterm; j += T) {
+            const TermDev tm = a.terms[S->term0 + j];
+            const double coef = tm.amp * profile_t(tm.ft_type, tm.c, tm.w, tm.k, tm.phi, ts);
+            sh_fyz[line][j] = (R)coef * rtab[tm.tab + n0 + yy] * rtab[tm.tab + n0 + n1 + zz];
+            if (line == 0) {
+                sh_mu[j] = tm.mu;
+                sh_tab[j] = tm.tab;
+            }
+        }
+        if (t == 0) sh_phyz[line] = cmul(gload<C>(ctab, S->ph + n0 + yy), gload<C>(ctab, S->ph + n0 + n1 + zz));
+    }
+    if (tid < 4) {
+        double sn, cs;
+        sincos(-S->E * ts, &sn, &cs);
+        const double wr = S->w[2 * tid], wi = S->w[2 * tid + 1];
+        sh_wc[tid] = cmake<C>((R)(wr * cs - wi * sn), (R)(wr * sn + wi * cs));
+    }
+    if constexpr (!VC::SITE) {
+        // the partner components through LDS
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[Lay::addr(0, 4 * line + q, t + T * m)] = yq[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            yx[m] = lds[Lay::addr(0, 4 * line + qx, t + T * m)];
+            yz[m] = lds[Lay::addr(0, 4 * line + qz, t + T * m)];
+            v[0][m] = yx[m];
+        }
+    }
+    // (alpha^1 D_x y)_q: the first exchange's barrier orders the reads above
+    // before the transform reuses the LDS
+    fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, 4 * line + q, tw);
+    const double kscale = S->dk[0] / (double)N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[0][m] = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
+    fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, 4 * line + q, tw);
+
+    // ---- stage epilogue
+    const R h = (R)(-a.dt);
+    const R h2 = (R)(-0.5 * a.dt), h6 = (R)(-a.dt / 6.0), third = (R)(1.0 / 3.0);
+    const C phyz = sh_phyz[line];
+    const R ky = (R)S->kap[1], kz = (R)S->kap[2];   // zero on non-trivial axes
+    const bool has_g = S->dim >= 2;
+    const long long mask = S->mask;
+    const R myz = (STAGE == 3 && mask >= 0) ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
+    // field A_mu at point idx of this line
+    auto field = [&](int idx, R (&A)[4]) {
+        A[0] = A[1] = A[2] = A[3] = (R)0;
+#pragma unroll
+        for (int jt = 0; jt < MAX_TERMS; ++jt) {
+            if (jt < nterm) {
+                const R f = sh_fyz[line][jt] * rtab[sh_tab[jt] + idx];
+                const int mu = sh_mu[jt];
+                A[0] += mu == 0 ? f : (R)0;
+                A[1] += mu == 1 ? f : (R)0;
+                A[2] += mu == 2 ? f : (R)0;
+                A[3] += mu == 3 ? f : (R)0;
+            }
+        }
+    };
+    if constexpr (VC::SITE) {
+        // whole sites: (alpha^1 D_x y) of all four components through LDS
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[Lay::addr(0, 4 * line + q, t + T * m)] = v[0][m];
+        __syncthreads();
+        const C wc[4] = {sh_wc[0], sh_wc[1], sh_wc[2], sh_wc[3]};
+        gptr<const nv2<R>> pg = cview<R>(S->buf[BUF_T]) + base;
+        gptr<const nv2<R>> pop = cview<R>(S->buf[STAGE == 3 ? BUF_ACC : BUF_Y]) + base;
+        gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base;
+        gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base;
+        gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base;
+#pragma unroll
+        for (int j = 0; j < (E + 3) / 4; ++j) {
+            const int m = q + 4 * j;
+            if (m < E) {
+                const int idx = t + T * m;
+                C y[4], g[4], y0[4], u[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    y[c] = gload_nt<C>(pin, c * ns + idx);
+                    g[c] = has_g ? gload_nt<C>(pg, c * ns + idx) : cmake<C>((R)0, (R)0);
+                    y0[c] = STAGE == 0 ? cmake<C>((R)0, (R)0) : gload_nt<C>(pop, c * ns + idx);
+                }
+                R A[4];
+                field(idx, A);
+                const C ph = cmul(gload<C>(ctab, S->ph + idx), phyz);
+                C sv[4], vs[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sv[c] = cadd(y[c], cmul(wc[c], ph));
+                apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
+                const R mk = (STAGE == 3 && mask >= 0) ? rtab[mask + idx] * myz : (R)1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const R bc = c < 2 ? (R)1 : (R)-1;
+                    C w = cadd(cadd(lds[Lay::addr(0, 4 * line + c, idx)], g[c]), cscale(y[c], bc));
+                    w = cadd(w, cadd(cscale(alpha2_phase(c, y[3 - c]), ky), cscale(alpha3_phase(c, y[c ^ 2]), kz)));
+                    u[c] = cmul_mi(cadd(w, vs[c]));   // k_c
+                }
+                // classical RK4 with the accumulator written once: with the stage
+                // inputs y_2 = y + h/2 k1, y_3 = y + h/2 k2, y_4 = y + h k3,
+                //   y_{n+1} = (y_2 + 2 y_3 - y)/3 + y_4/3 + h/6 k4,
+                // so stage 1 stores acc = (y_2 + 2 y_3 - y)/3 and stage 3 finishes
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const C k = u[c];
+                    if constexpr (STAGE == 0) {
+                        if (act) gstore_nt<C>(wys, c * ns + idx, cadd(y[c], cscale(k, h2)));             // y_2
+                    } else if constexpr (STAGE == 1) {
+                        const C y3 = cadd(y0[c], cscale(k, h2));                                          // y_3
+                        if (act) {
+                            gstore_nt<C>(wacc, c * ns + idx, cscale(csub(cadd(y[c], cscale(y3, (R)2)), y0[c]), third));
+                            gstore_nt<C>(wys, c * ns + idx, y3);
+                        }
+                    } else if constexpr (STAGE == 2) {
+                        if (act) gstore_nt<C>(wys, c * ns + idx, cadd(y0[c], cscale(k, h)));             // y_4
+                    } else {
+                        if (act) gstore_nt<C>(wy, c * ns + idx, cscale(cadd(cadd(y0[c], cscale(y[c], third)), cscale(k, h6)), mk));
+                    }
+                }
+            }
+        }
+    } else {
+        // component q at the thread's own points
+        const C wq = sh_wc[q], wx = sh_wc[qx], wz = sh_wc[qz];
+        const R bq = q < 2 ? (R)1 : (R)-1;
+        gptr<const nv2<R>> pg = cview<R>(S->buf[BUF_T]) + base + q * ns + t;
+        gptr<const nv2<R>> py = cview<R>(S->buf[BUF_Y]) + base + q * ns + t;
+        gptr<const nv2<R>> pacc = cview<R>(S->buf[BUF_ACC]) + base + q * ns + t;
+        gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base + q * ns + t;
+        gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base + q * ns + t;
+        gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base + q * ns + t;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int idx = t + T * m;
+            const C g = has_g ? gload_nt<C>(pg, T * m) : cmake<C>((R)0, (R)0);
+            C y0 = cmake<C>((R)0, (R)0);
+            if constexpr (STAGE == 1 || STAGE == 2) y0 = gload_nt<C>(py, T * m);
+            if constexpr (STAGE == 3) y0 = gload_nt<C>(pacc, T * m);
+            R A[4];
+            field(idx, A);
+            const C ph = cmul(gload<C>(ctab, S->ph + idx), phyz);
+            // y + psi_b on the three components
+            const C sq = cadd(yq[m], cmul(wq, ph)), sx = cadd(yx[m], cmul(wx, ph)), sz = cadd(yz[m], cmul(wz, ph));
+            // [alpha^1 D_x y + G + beta y + kappa terms + A0 s + (A1 alpha^1 + A2 alpha^2) s + A3 alpha^3 s]_q
+            C u = cadd(cadd(v[0][m], g), cscale(yq[m], bq));
+            u = cadd(u, cadd(cscale(alpha2_phase(q, yx[m]), ky), cscale(alpha3_phase(q, yz[m]), kz)));
+            u = cadd(u, cscale(sq, A[0]));
+            u = cadd(u, cadd(cscale(sx, A[1]), cscale(alpha2_phase(q, sx), A[2])));
+            u = cadd(u, cscale(alpha3_phase(q, sz), A[3]));
+            const C k = cmul_mi(u);
+            // classical RK4 with the accumulator written once (as above)
+            if constexpr (STAGE == 0) {
+                if (act) gstore_nt<C>(wys, T * m, cadd(yq[m], cscale(k, h2)));                    // y_2
+            } else if constexpr (STAGE == 1) {
+                const C y3 = cadd(y0, cscale(k, h2));                                              // y_3
+                if (act) {
+                    gstore_nt<C>(wacc, T * m, cscale(csub(cadd(yq[m], cscale(y3, (R)2)), y0), third));
+                    gstore_nt<C>(wys, T * m, y3);
+                }
+            } else if constexpr (STAGE == 2) {
+                if (act) gstore_nt<C>(wys, T * m, cadd(y0, cscale(k, h)));                          // y_4
+            } else {
+                const R mk = mask >= 0 ? rtab[mask + idx] * myz : (R)1;
+                if (act) gstore_nt<C>(wy, T * m, cscale(cadd(cadd(y0, cscale(yq[m], third)), cscale(k, h6)), mk));
+            }
+        }
     }
 }
 
@@ -953,15 +958,16 @@ __global__ void __launch_bounds__((LineVar<R, N, WIDE>::T)) line_kernel(PassArgs
 
 // Kernel table of one (precision, N) instantiation.
 struct RowVariant { const void* stage[4]; int threads, rows; size_t lds; };
+struct CdVariant { const void* fn[2][2]; int threads, w; size_t lds; };   // [axis - 1][accumulate]
 struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
-    int nvar;                      // row-pass variants
-    int nvar_col;                  // column-pass variants
-    RowVariant row[NVAR];          // the RK4 stage pass, by variant
-    const void* row_other[ROW_NMODES];  // other row modes (variant 0)
+    int nvar;                      // tile variants of the stepping passes
+    RowVariant row[NVAR];          // the RK4 stage row pass, by variant
+    CdVariant cd[NVAR];            // the stepping column passes, by variant
+    const void* row_other[ROW_NMODES];  // whole-state row modes
     int row0_threads, row0_rows;
     size_t row0_lds;
-    ColVariant col[NVAR];
+    ColVariant col;                // whole-state column transforms
     const void* line[2];           // 1D whole-loop kernel, narrow / wide exchange rounds
                                    // (NULL where there is no 4-point plan)
     int line_threads;
@@ -970,17 +976,23 @@ struct SizeKernels {
 
 template <class R, int N, int V>
 RowVariant make_row_variant() {
-    using VC = RowVar<R, N, V>;
-    return RowVariant{{(const void*)row_kernel<R, N, V, ROW_STAGE, 0>, (const void*)row_kernel<R, N, V, ROW_STAGE, 1>,
-                       (const void*)row_kernel<R, N, V, ROW_STAGE, 2>, (const void*)row_kernel<R, N, V, ROW_STAGE, 3>},
+    using VC = RdVar<R, N, V>;
+    return RowVariant{{(const void*)row_d_kernel<R, N, V, 0>, (const void*)row_d_kernel<R, N, V, 1>,
+                       (const void*)row_d_kernel<R, N, V, 2>, (const void*)row_d_kernel<R, N, V, 3>},
                       VC::THREADS, VC::ROWS, VC::BYTES};
 }
 template <class R, int N, int V>
-RowVariant make_row_cs_variant() {
-    using VC = RowCsVar<R, N, V>;
-    return RowVariant{{(const void*)row_cs_kernel<R, N, V, 0>, (const void*)row_cs_kernel<R, N, V, 1>,
-                       (const void*)row_cs_kernel<R, N, V, 2>, (const void*)row_cs_kernel<R, N, V, 3>},
-                      VC::THREADS, VC::ROWS, VC::BYTES};
+CdVariant make_cd_variant() {
+    using VC = CdVar<R, N, V>;
+    CdVariant c;
+    c.fn[0][0] = (const void*)col_d_kernel<R, N, V, 1, 0>;
+    c.fn[0][1] = (const void*)col_d_kernel<R, N, V, 1, 1>;
+    c.fn[1][0] = (const void*)col_d_kernel<R, N, V, 2, 0>;
+    c.fn[1][1] = (const void*)col_d_kernel<R, N, V, 2, 1>;
+    c.threads = VC::THREADS;
+    c.w = VC::W;
+    c.lds = VC::BYTES;
+    return c;
 }
 template <class R, int N, int V>
 ColVariant make_col_variant() {
@@ -1002,28 +1014,25 @@ template <class R, int N>
 SizeKernels make_size_kernels() {
     SizeKernels k;
     k.nvar = nvar<N>();
-    k.nvar_col = nvar_col<N>();
     k.row[0] = make_row_variant<R, N, 0>();
-    k.col[0] = make_col_variant<R, N, 0>();
+    k.cd[0] = make_cd_variant<R, N, 0>();
     if constexpr (nvar<N>() > 1) {
         k.row[1] = make_row_variant<R, N, 1>();
         k.row[2] = make_row_variant<R, N, 2>();
         k.row[3] = make_row_variant<R, N, 3>();
-        k.row[4] = make_row_cs_variant<R, N, 4>();
-        k.row[5] = make_row_cs_variant<R, N, 5>();
-        k.col[1] = make_col_variant<R, N, 1>();
-        k.col[2] = make_col_variant<R, N, 2>();
-        k.col[3] = make_col_variant<R, N, 3>();
-        k.col[4] = k.col[2];
-        k.col[5] = k.col[3];
+        k.cd[1] = make_cd_variant<R, N, 1>();
+        k.cd[2] = make_cd_variant<R, N, 2>();
+        k.cd[3] = make_cd_variant<R, N, 3>();
     } else {
         for (int v = 1; v < NVAR; ++v) {
             k.row[v] = k.row[0];
-            k.col[v] = k.col[0];
+            k.cd[v] = k.cd[0];
         }
     }
+    // whole-state column transforms: the few-points plan where there is one
+    k.col = make_col_variant<R, N, (nvar<N>() > 1 && has_small_plan<N>()) ? 2 : 0>();
     k.row_other[ROW_FWD] = (const void*)row_kernel<R, N, 0, ROW_FWD, 0>;
-    k.row_other[ROW_STAGE] = (const void*)row_kernel<R, N, 0, ROW_STAGE, 0>;
+    k.row_other[ROW_STAGE] = nullptr;
     k.row_other[ROW_INV] = (const void*)row_kernel<R, N, 0, ROW_INV, 0>;
     k.row_other[ROW_RHS] = (const void*)row_kernel<R, N, 0, ROW_RHS, 0>;
     k.row_other[ROW_FWDPH] = (const void*)row_kernel<R, N, 0, ROW_FWDPH, 0>;
