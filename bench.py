@@ -143,7 +143,7 @@ def observables(ctx, prob):
 
 
 def run_path(S, torch, prob, precision, K, Wm, batched=True, tune=True, variant=None, chunk=0, graph=False,
-             bw_partial=False, max_solves=0, label="", reset_after_warmup=False):
+             bw_partial=False, max_solves=0, label="", reset_after_warmup=False, tune_cache=None):
     """Time K RK4 steps (after Wm untimed ones) of every solve of prob.
     With reset_after_warmup the context is returned to t_out after the Wm
     steps, so the K timed steps can span the whole window.
@@ -161,7 +161,7 @@ def run_path(S, torch, prob, precision, K, Wm, batched=True, tune=True, variant=
         print(f"[bench] {label}: context of {len(b)} solves, {len(sub.vertices)} vertices, "
               f"{S.workspace_size(sub, precision, bw_partial) / 1e9:.1f} GB", file=sys.stderr, flush=True)
         ctx = S.Context(sub, precision=precision, batched=batched, use_graph=graph, profile=not graph, tune=tune,
-                        chunk=chunk, variant=variant, bw_partial=bw_partial)
+                        chunk=chunk, variant=variant, bw_partial=bw_partial, tune_cache=tune_cache)
         reports.append(ctx.tune_report())
         if Wm:
             ctx.step(Wm)
@@ -236,24 +236,30 @@ def stored_traffic(kind, precision, n, report, variant):
     if t.get("kernel_source_sha256") != source_hash():
         return None
     real = "double" if precision == "fp64" else "float"
-    tag = {0: "row", 1: "col1", 2: "col2"}.get(kind)
+    tag = {0: "row", 1: "col1", 2: "col2", 3: "bw"}.get(kind)
     if tag is None:
         return None
-    if variant is None:
-        # the variant the autotuner kept: the fastest one it timed
-        times = {}
-        for m in re.finditer(rf"{tag} v(\d+) ([0-9.eE+-]+) ms", report):
-            v, ms = int(m.group(1)), float(m.group(2))
-            times[v] = min(ms, times.get(v, ms))
-        if not times:
-            return None
-        variant = min(times, key=times.get)
+    if variant is None and kind != 3:
+        # the variant the autotuner kept: the fastest one it timed, or the cached choice
+        cached = re.search(r"cached (\d+) (\d+) (\d+)", report)
+        if cached:
+            variant = int(cached.group(1 + kind))
+        else:
+            times = {}
+            for m in re.finditer(rf"{tag} v(\d+) ([0-9.eE+-]+) ms", report):
+                v, ms = int(m.group(1)), float(m.group(2))
+                times[v] = min(ms, times.get(v, ms))
+            if not times:
+                return None
+            variant = min(times, key=times.get)
     if kind == 0:
-        names = [f"void swf::row_kernel<{real}, {n}, {variant}, 1, {s}>(swf::PassArgs)" for s in range(4)]
+        names = [f"void swf::row_d_kernel<{real}, {n}, {variant}, {s}>(swf::PassArgs)" for s in range(4)]
     elif kind == 1:
-        names = [f"void swf::col_kernel<{real}, {n}, {variant}, {m}, 1>(swf::PassArgs)" for m in (0, 1)]
+        names = [f"void swf::col_d_kernel<{real}, {n}, {variant}, 1, 0>(swf::PassArgs)"]
+    elif kind == 2:
+        names = [f"void swf::col_d_kernel<{real}, {n}, {variant}, 2, 1>(swf::PassArgs)"]
     else:
-        names = [f"void swf::col_kernel<{real}, {n}, {variant}, 2, 2>(swf::PassArgs)"]
+        names = [f"void swf::bw_stage_kernel<{real}>(swf::BwArgs)"]
     vals = []
     for nm in names:
         k = t["kernels"].get(nm)
@@ -475,6 +481,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="solves per launch group (0 = all)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile variants")
     ap.add_argument("--variant", type=int, default=None, help="force tile variant 0..3 for every pass")
+    ap.add_argument("--tune-cache", default=None, metavar="FILE",
+                    help="autotuner cache: tile choices are read from FILE and new ones appended")
     ap.add_argument("--bw-partial", action="store_true",
                     help="also integrate the BW vertices by the partial-integration route (timed with the steps)")
     ap.add_argument("--pair-matrix", type=int, default=0, metavar="N",
@@ -534,7 +542,7 @@ def main():
 
     def leg(name, precision, **kw):
         wall, t_obs, obs, stats, reps, subs, extra = run_path(
-            S, torch, prob, precision, K, Wm, reset_after_warmup=args.full_window,
+            S, torch, prob, precision, K, Wm, reset_after_warmup=args.full_window, tune_cache=args.tune_cache,
             tune=kw.pop("tune", not args.no_tune),
             variant=kw.pop("variant", args.variant), chunk=args.chunk, bw_partial=args.bw_partial,
             max_solves=args.max_solves, label=name, **kw)

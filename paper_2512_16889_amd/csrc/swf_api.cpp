@@ -184,13 +184,14 @@ struct Plan {
     std::vector<SolveDev> hs;           // buf pointers filled after allocation (offsets meanwhile)
     std::vector<TermDev> ht;
     std::vector<VertexDev> hv;
+    std::vector<swf::VertexGroupDev> hg;  // vertex groups of the stage reduction
     std::vector<double> rtab;           // real tables (rounded to the state precision on upload)
     std::vector<cd> ctab;               // complex tables
     std::vector<Group> batched, single; // groups per grid / per solve
     std::vector<int2> items;
     size_t state_bytes = 0;             // all state arrays
     // arena layout (byte offsets)
-    size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_rtab = 0, off_ctab = 0,
+    size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_vgroups = 0, off_rtab = 0, off_ctab = 0,
            off_items = 0, off_step = 0, off_M = 0, off_part = 0, off_red = 0, off_M2 = 0, off_part2 = 0, total = 0;
     std::vector<size_t> solve_off;      // state offset of each solve (bytes from off_state)
     bool bw2 = false;                   // partial-integration BW route on
@@ -473,6 +474,43 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         d.phk = (long long)add_c(ph);
         P.hv.push_back(d);
     }
+    // vertices reduced together: greedily, at most 2 U and 2 V solves and 4
+    // vertices of one grid and one photon per group, so a solve shared by
+    // several vertices is read once per stage
+    auto same_photon = [&](int v, int w) {
+        for (int j = 0; j < 3; ++j)
+            if (P.verts[v].k[j] != P.verts[w].k[j] || P.verts[v].eps[j] != P.verts[w].eps[j]) return false;
+        return true;
+    };
+    for (int v = 0; v < n_verts; ++v) {
+        const int su = P.verts[v].u_solve, sv = P.verts[v].v_solve;
+        bool placed = false;
+        for (auto& g : P.hg) {
+            if (g.nvx >= swf::BWG_VERTS || P.solves[g.su[0]].grid != P.solves[su].grid || !same_photon(g.vtx[0], v))
+                continue;
+            int ui = -1, vi = -1;
+            for (int k = 0; k < g.nu; ++k) if (g.su[k] == su) ui = k;
+            for (int k = 0; k < g.nv; ++k) if (g.sv[k] == sv) vi = k;
+            if ((ui < 0 && g.nu >= swf::BWG_SOLVES) || (vi < 0 && g.nv >= swf::BWG_SOLVES)) continue;
+            if (ui < 0) { ui = g.nu; g.su[g.nu++] = su; }
+            if (vi < 0) { vi = g.nv; g.sv[g.nv++] = sv; }
+            g.vtx[g.nvx] = v;
+            g.ui[g.nvx] = ui;
+            g.vi[g.nvx] = vi;
+            ++g.nvx;
+            placed = true;
+            break;
+        }
+        if (!placed) {
+            swf::VertexGroupDev g;
+            memset(&g, 0, sizeof(g));
+            g.nu = g.nv = g.nvx = 1;
+            g.su[0] = su;
+            g.sv[0] = sv;
+            g.vtx[0] = v;
+            P.hg.push_back(g);
+        }
+    }
     // ---- groups and work items
     if (opt->chunk < 0) FAIL(SWF_E_ARG, "chunk must be >= 0");
     if (opt->check_every < 0) FAIL(SWF_E_ARG, "check_every must be >= 0");
@@ -516,6 +554,8 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     off += sizeof(TermDev) * std::max<size_t>(1, P.ht.size());
     P.off_verts = off = align256(off);
     off += sizeof(VertexDev) * std::max(1, n_verts);
+    P.off_vgroups = off = align256(off);
+    off += sizeof(swf::VertexGroupDev) * std::max<size_t>(1, P.hg.size());
     P.off_rtab = off = align256(off);
     off += P.rsize * std::max<size_t>(1, P.rtab.size());
     P.off_ctab = off = align256(off);
@@ -575,6 +615,7 @@ struct swf_ctx {
     SolveDev* d_solves() { return (SolveDev*)(arena + P.off_solves); }
     TermDev* d_terms() { return (TermDev*)(arena + P.off_terms); }
     VertexDev* d_verts() { return (VertexDev*)(arena + P.off_verts); }
+    swf::VertexGroupDev* d_vgroups() { return (swf::VertexGroupDev*)(arena + P.off_vgroups); }
     void* d_rtab() { return arena + P.off_rtab; }
     void* d_ctab() { return arena + P.off_ctab; }
     int2* d_items() { return (int2*)(arena + P.off_items); }
@@ -783,6 +824,7 @@ static int bw_stage(swf_ctx* ctx, int stage) {
     b.nvert = (int)ctx->P.hv.size();
     b.part = ctx->d_part();
     b.M = ctx->d_M();
+    b.groups = ctx->d_vgroups();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = ctx->opt.profile && !ctx->gexec;
     if (prof) {
@@ -791,10 +833,11 @@ static int bw_stage(swf_ctx* ctx, int stage) {
         if (r) return r;
         HIPCHK(hipEventRecord(e0, ctx->st));
     }
-    HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, ctx->st));
+    HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.hg.size(), ctx->st));
     if (prof) {
+        // every state of a group's solves is read once
         double bytes = 0;
-        for (auto& v : ctx->P.hv) bytes += 2.0 * 4.0 * ctx->P.csize * (double)ctx->P.hs[v.su].nsites;
+        for (auto& g : ctx->P.hg) bytes += (g.nu + g.nv) * 4.0 * ctx->P.csize * (double)ctx->P.hs[g.su[0]].nsites;
         HIPCHK(hipEventRecord(e1, ctx->st));
         ctx->pending.push_back({e0, e1, 3, bytes});
     }
@@ -1496,6 +1539,9 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         INITCHK(hipMemcpyAsync(ctx->d_terms(), P.ht.data(), sizeof(TermDev) * P.ht.size(), hipMemcpyHostToDevice, ctx->st));
     if (!P.hv.empty())
         INITCHK(hipMemcpyAsync(ctx->d_verts(), P.hv.data(), sizeof(VertexDev) * P.hv.size(), hipMemcpyHostToDevice, ctx->st));
+    if (!P.hg.empty())
+        INITCHK(hipMemcpyAsync(ctx->d_vgroups(), P.hg.data(), sizeof(swf::VertexGroupDev) * P.hg.size(),
+                               hipMemcpyHostToDevice, ctx->st));
     std::vector<char> rt(P.rsize * std::max<size_t>(1, P.rtab.size())), ct(P.csize * std::max<size_t>(1, P.ctab.size()));
     for (size_t i = 0; i < P.rtab.size(); ++i) {
         if (P.fp64) ((double*)rt.data())[i] = P.rtab[i];

@@ -34,9 +34,21 @@ struct VertexDev {
     double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
 };
 
+// Vertices reduced together at each RK4 stage: every state of the group's (at
+// most 2) U and (at most 2) V solves is read once for all its vertices.
+constexpr int BWG_SOLVES = 2;
+constexpr int BWG_VERTS = 4;
+struct VertexGroupDev {
+    int nu, nv, nvx;
+    int su[BWG_SOLVES], sv[BWG_SOLVES];   // the solves
+    int vtx[BWG_VERTS];                   // the vertices
+    int ui[BWG_VERTS], vi[BWG_VERTS];     // each vertex's U and V solve within su / sv
+};
+
 struct BwArgs {
     const SolveDev* solves;
     const VertexDev* verts;
+    const VertexGroupDev* groups;   // the first route's stage reduction, one group per blockIdx.y
     const void* ctab;
     const int* step;
     double t_out, dt;
@@ -78,7 +90,7 @@ struct PairArgs {
 
 hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
 hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
-hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st);
+hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_bw2_src(int fp64, const BwArgs& a, int blocks, hipStream_t st);
 hipError_t launch_bw2_kss(int fp64, const BwArgs& a, int blocks, hipStream_t st);

@@ -200,70 +200,130 @@ __global__ void __launch_bounds__(RED_THREADS) xspace_diag_kernel(RedArgs a) {
 
 // Breit-Wheeler integrand of eq. (Mabfinite) at one RK4 stage for every vertex:
 // Mdot_ab = sum_x e^{-i(k0 t - k.x)} Ua^dag (alpha.eps) Vb for (s,s), (b,s), (s,b).
+// One group of vertices per blockIdx.y, all with the same photon: per site the
+// stage inputs of the group's V solves are read and multiplied by alpha.eps
+// once, then each U solve is read once and dotted with them for its vertices.
 template <class R>
 __global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
     using C = cpx<R>;
-    const VertexDev* V = a.verts + blockIdx.y;
-    const SolveDev* SU = a.solves + V->su;
-    const SolveDev* SV = a.solves + V->sv;
+    const VertexGroupDev G = a.groups[blockIdx.y];
     const int role = a.stage == 0 ? BUF_Y : BUF_YS;
-    const C* U = reinterpret_cast<const C*>(SU->buf[role]);
-    const C* W = reinterpret_cast<const C*>(SV->buf[role]);
-    const C* ctab = reinterpret_cast<const C*>(a.ctab);
-    const C* phU = ctab + SU->ph;
-    const C* phV = ctab + SV->ph;
-    const C* phK = ctab + V->phk;
     const int n = *a.step;
     const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
     const double ts = a.t_out - (double)n * a.dt - cst * a.dt;
-    double2 wcU[4], wcV[4];
-    {
-        double sn, cs;
-        sincos(-SU->E * ts, &sn, &cs);
-        for (int q = 0; q < 4; ++q) wcU[q] = dmul(d2(SU->w[2 * q], SU->w[2 * q + 1]), d2(cs, sn));
-        sincos(-SV->E * ts, &sn, &cs);
-        for (int q = 0; q < 4; ++q) wcV[q] = dmul(d2(SV->w[2 * q], SV->w[2 * q + 1]), d2(cs, sn));
-    }
+    const C* ctab = reinterpret_cast<const C*>(a.ctab);
+    const SolveDev* S0 = a.solves + G.su[0];
+    const int n0 = S0->n[0], n1 = S0->n[1];
+    const long long ns = S0->nsites;
+    const VertexDev* V0 = a.verts + G.vtx[0];
     double snk, csk;
-    sincos(-V->k0 * ts, &snk, &csk);
+    sincos(-V0->k0 * ts, &snk, &csk);
     const double2 ek = d2(csk, snk);
-    const int n0 = SU->n[0], n1 = SU->n[1];
-    const long long ns = SU->nsites;
-    double2 acc[3] = {d2(0, 0), d2(0, 0), d2(0, 0)};
+    const C* phK = ctab + V0->phk;
+    const double* eps = V0->eps;
+    // exp(-i E t) of the group's solves, once per launch
+    double2 eu[BWG_SOLVES], ev[BWG_SOLVES];
+#pragma unroll
+    for (int u = 0; u < BWG_SOLVES; ++u) {
+        double sn, cs;
+        sincos(-a.solves[G.su[u < G.nu ? u : 0]].E * ts, &sn, &cs);
+        eu[u] = d2(cs, sn);
+        sincos(-a.solves[G.sv[u < G.nv ? u : 0]].E * ts, &sn, &cs);
+        ev[u] = d2(cs, sn);
+    }
+    double acc[BWG_VERTS][3][2];
+#pragma unroll
+    for (int j = 0; j < BWG_VERTS; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[j][c][0] = acc[j][c][1] = 0.0;
     for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
         const int x = (int)(i % n0);
         const long long r = i / n0;
         const int y = (int)(r % n1), z = (int)(r / n1);
-        const double2 pu = todbl(cmul(cmul(phU[x], phU[n0 + y]), phU[n0 + n1 + z]));
-        const double2 pv = todbl(cmul(cmul(phV[x], phV[n0 + y]), phV[n0 + n1 + z]));
+        // V side: (alpha.eps) V_scat and (alpha.eps) V_back of each V solve
+        double2 gyv[BWG_SOLVES][4], gbv[BWG_SOLVES][4];
+#pragma unroll
+        for (int b = 0; b < BWG_SOLVES; ++b) {
+            if (b < G.nv) {
+                const SolveDev* SV = a.solves + G.sv[b];
+                const C* W = reinterpret_cast<const C*>(SV->buf[role]);
+                const C* ph = ctab + SV->ph;
+                const double2 pv = dmul(ev[b], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
+                double2 yv[4], bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    yv[q] = todbl(W[q * ns + i]);
+                    bv[q] = dmul(d2(SV->w[2 * q], SV->w[2 * q + 1]), pv);
+                }
+                gam_eps(yv, gyv[b], eps);
+                gam_eps(bv, gbv[b], eps);
+            }
+        }
         const double2 pk = dmul(ek, todbl(cmul(cmul(phK[x], phK[n0 + y]), phK[n0 + n1 + z])));
-        double2 yu[4], yv[4], bu[4], bv[4], gyv[4], gbv[4];
+        const double2 pkc = d2(pk.x, -pk.y);   // conj(U) pk = conj(U conj(pk))
+        // U side, one solve at a time, against the V side of each of its vertices
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            yu[q] = todbl(U[q * ns + i]);
-            yv[q] = todbl(W[q * ns + i]);
-            bu[q] = dmul(wcU[q], pu);
-            bv[q] = dmul(wcV[q], pv);
-        }
-        gam_eps(yv, gyv, V->eps);
-        gam_eps(bv, gbv, V->eps);
-        double2 s0 = d2(0, 0), s1 = d2(0, 0), s2 = d2(0, 0);
+        for (int u = 0; u < BWG_SOLVES; ++u) {
+            if (u < G.nu) {
+                const SolveDev* SU = a.solves + G.su[u];
+                const C* U = reinterpret_cast<const C*>(SU->buf[role]);
+                const C* ph = ctab + SU->ph;
+                const double2 pu = dmul(eu[u], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
+                double2 yu[4], bu[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            s0 = dadd(s0, dcmul(yu[q], gyv[q]));
-            s1 = dadd(s1, dcmul(bu[q], gyv[q]));
-            s2 = dadd(s2, dcmul(yu[q], gbv[q]));
+                for (int q = 0; q < 4; ++q) {
+                    yu[q] = dmul(todbl(U[q * ns + i]), pkc);                      // the photon phase folded in
+                    bu[q] = dmul(dmul(d2(SU->w[2 * q], SU->w[2 * q + 1]), pu), pkc);
+                }
+#pragma unroll
+                for (int j = 0; j < BWG_VERTS; ++j) {
+                    if (j < G.nvx && G.ui[j] == u) {
+                        const int vi = G.vi[j];
+                        double2 s0 = d2(0, 0), s1 = d2(0, 0), s2 = d2(0, 0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double2 gy = vi ? gyv[1][q] : gyv[0][q];
+                            const double2 gb = vi ? gbv[1][q] : gbv[0][q];
+                            s0 = dadd(s0, dcmul(yu[q], gy));
+                            s1 = dadd(s1, dcmul(bu[q], gy));
+                            s2 = dadd(s2, dcmul(yu[q], gb));
+                        }
+                        acc[j][0][0] += s0.x; acc[j][0][1] += s0.y;
+                        acc[j][1][0] += s1.x; acc[j][1][1] += s1.y;
+                        acc[j][2][0] += s2.x; acc[j][2][1] += s2.y;
+                    }
+                }
+            }
         }
-        acc[0] = dadd(acc[0], dmul(pk, s0));
-        acc[1] = dadd(acc[1], dmul(pk, s1));
-        acc[2] = dadd(acc[2], dmul(pk, s2));
     }
-    // partials layout [vertex][stage][block][3]
-    double2* out = a.part + ((long long)blockIdx.y * 4 + a.stage) * (long long)gridDim.x * 3;
-    block_sum_store<3>(acc, out);
+    // block sums of the 3 terms of every vertex: a fixed butterfly within each
+    // wave, then the waves in order; partials layout [vertex][stage][block][3]
+    constexpr int NV = 3 * BWG_VERTS;
+    constexpr int NW = RED_THREADS / 64;
+    __shared__ double2 shw[NW][NV];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+#pragma unroll
+    for (int j = 0; j < BWG_VERTS; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 v = d2(acc[j][c][0], acc[j][c][1]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v.x += __shfl_down(v.x, off, 64);
+                v.y += __shfl_down(v.y, off, 64);
+            }
+            if (lane == 0) shw[wave][3 * j + c] = v;
+        }
+    __syncthreads();
+    if (tid < 3 * G.nvx) {
+        double2 v = shw[0][tid];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v = dadd(v, shw[w][tid]);
+        const int j = tid / 3, c = tid % 3;
+        a.part[(((long long)G.vtx[j] * 4 + a.stage) * gridDim.x + blockIdx.x) * 3 + c] = v;
+    }
 }
 
-// M_ab += (h/6) dV (d0 + 2 d1 + 2 d2 + d3), partial sums added in a fixed order.
 __global__ void bw_accum_kernel(BwArgs a, int nblk) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= a.nvert * 3) return;
@@ -526,8 +586,8 @@ hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hi
     return fp64 ? launch_red<double>(kind, a, blocks, st) : launch_red<float>(kind, a, blocks, st);
 }
 
-hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, hipStream_t st) {
-    dim3 g(blocks, a.nvert), b(RED_THREADS);
+hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, hipStream_t st) {
+    dim3 g(blocks, ngroups), b(RED_THREADS);
     if (fp64) hipLaunchKernelGGL(bw_stage_kernel<double>, g, b, 0, st, a);
     else hipLaunchKernelGGL(bw_stage_kernel<float>, g, b, 0, st, a);
     return hipGetLastError();
