@@ -72,7 +72,7 @@ def workload(name):
                                "dt=0.025, 4000-step window, 8 solves")
     if name == "ragged":
         return W.config_ragged_2d(), ("(2+1)D ragged batch: 256 solves, n in {256,384,512,768,1024}, "
-                                      "Gaussian fields from seed 0, dt=0.02, 6000-step window")
+                                      "Gaussian fields from seed 0, dt=0.02, 8000-step window")
     if name == "1d":
         return W.config_1d(), ("(1+1)D Schwinger: A_1 = 1.5 sech^2(0.2 t) sech^2(0.1 x), n=1024 over [-100,100), "
                                "dt=0.02, 6000-step window, one solve")

@@ -135,6 +135,22 @@ def test_launch_config_3d_256_x8_pure_gauge(S, prec):
     pure_gauge_check(S, prob, lam0, tau, w, prec, prob.window.steps)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_launch_config_ragged_256_pure_gauge(S, prec):
+    # the ragged batch's own launch configuration: 256 solves on the five grid
+    # sizes of the seed-0 draw (one launch group per size, the 1024^2 group
+    # with its XCD-grouped column tiles), one pure-gauge field for all
+    lam0, tau, w = 0.8, 2.0, 10.0
+    prob = W.config_ragged_2d()
+    sizes = sorted(set(g.n[0] for g in prob.grids))
+    assert sizes == [256, 384, 512, 768, 1024] and len(prob.solves) == 256
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 2)]
+    for s in prob.solves:
+        s.field = 0
+    prob.window = W.Window(0.0, 12.0, 0.02)            # Lambda(t_out) ~ 1e-16; ends at the pulse maximum
+    pure_gauge_check(S, prob, lam0, tau, w, prec, prob.window.steps, nsample=512)
+
+
 def test_launch_config_3d_320_pure_gauge(S):
     lam0, tau, w = 0.8, 2.0, 8.0
     prob = W.config_bw_3d(n_p=1)
@@ -190,17 +206,20 @@ def pure_gauge_bw_reference(prob, lam0, tau, w, nsteps):
     return out
 
 
+@pytest.mark.parametrize("photons", ["one", "four"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-5), ("mixed", 3e-4)])
-def test_launch_config_bw_320_pure_gauge(S, prec, tol):
+def test_launch_config_bw_320_pure_gauge(S, prec, tol, photons):
     # the BW vertex reduction in the 320^3 launch configuration (one momentum,
-    # four spin pairs: 2 U + 2 V solves, 4 vertices) against the closed form;
-    # each vertex gets its own photon so that every vertex has its own value
+    # four spin pairs: 2 U + 2 V solves, 4 vertices) against the closed form:
+    # with the workload's one photon the four vertices are reduced as one
+    # group (each solve read once); with four photons, one group each
     lam0, tau, w = 0.8, 2.0, 8.0
     prob = W.config_bw_3d(n_p=1)
     prob.fields = [W.field_pure_gauge(lam0, tau, w, 3)]
-    photons = [([0.0, 0.0, 2.0], [-1.0, 0.0, 0.0]), ([0.3, 0.0, 1.9], [0.0, 1.0, 0.0]),
-               ([0.0, -0.4, 1.8], [0.6, 0.0, 0.8]), ([0.2, 0.25, 2.2], [0.0, 0.8, -0.6])]
-    prob.vertices = [W.Vertex(vx.u_solve, vx.v_solve, k, e) for vx, (k, e) in zip(prob.vertices, photons)]
+    if photons == "four":
+        ks = [([0.0, 0.0, 2.0], [-1.0, 0.0, 0.0]), ([0.3, 0.0, 1.9], [0.0, 1.0, 0.0]),
+              ([0.0, -0.4, 1.8], [0.6, 0.0, 0.8]), ([0.2, 0.25, 2.2], [0.0, 0.8, -0.6])]
+        prob.vertices = [W.Vertex(vx.u_solve, vx.v_solve, k, e) for vx, (k, e) in zip(prob.vertices, ks)]
     prob.window = W.Window(0.0, 8.0, 0.05)             # Lambda(t_out) ~ 1e-7, ends at the pulse maximum
     nsteps = prob.window.steps
     ref = pure_gauge_bw_reference(prob, lam0, tau, w, nsteps)
@@ -249,3 +268,22 @@ def test_row_pass_variants_with_absorber(S, variant, prec, tol):
             ref = SWFSolve(prob, i).run(states[i], start=k0, count=3)
             err = relerr(ctx.get_psi(i), ref)
             assert err < tol, (prec, variant, i, err)
+
+
+def test_bw_320_shape_mixed_against_fp64_full_window(S):
+    """The Breit-Wheeler workload's shape over its whole 3000-step window on a
+    48^3 lattice over the same box (32 solves, 32 vertices): the mixed path's
+    |M|^2 of every vertex against the FP64 path's, to the 1e-4 the benchmark
+    states for the mixed path."""
+    import dataclasses
+    prob = W.config_bw_3d()
+    prob = dataclasses.replace(prob, grids=[dataclasses.replace(prob.grids[0], n=[48, 48, 48])])
+    vals = {}
+    for prec in ("fp64", "mixed"):
+        with S.Context(prob, precision=prec) as ctx:
+            ctx.step()
+            vals[prec] = np.array([abs(ctx.bw(v)) ** 2 for v in range(len(prob.vertices))])
+    assert vals["fp64"].min() > 0
+    err = np.abs(vals["mixed"] - vals["fp64"]) / vals["fp64"]
+    print(f"48^3 full window: max rel |M|^2 error mixed vs fp64 {err.max():.3e}")
+    assert err.max() < 1e-4

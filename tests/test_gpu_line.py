@@ -187,3 +187,34 @@ def test_line_kernel_with_graph_option(S):
             e.step(c)
             for i in range(len(prob.solves)):
                 assert np.array_equal(g.get_psi(i), e.get_psi(i))
+
+
+_C1_REF = {}
+
+
+def c1_reference():
+    """The (1+1)D Schwinger workload over its whole window (1024 points,
+    6000 RK4 steps from t = 60 to -60) by the oracle, computed once."""
+    if not _C1_REF:
+        prob = W.config_1d()
+        sv = SWFSolve(prob, 0)
+        y = sv.run()
+        _C1_REF.update(prob=prob, sv=sv, y=y, P=ob.marginal(sv, y))
+    return _C1_REF
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_c1_full_window_vs_oracle(S, persistent):
+    """The whole 6000-step (1+1)D workload, by the whole-loop kernel and by the
+    pass path, against the oracle: psi element by element to 1e-10 of its
+    largest value and the marginal P to 1e-9."""
+    ref = c1_reference()
+    prob = ref["prob"]
+    with S.Context(prob, precision="fp64", persistent=persistent, profile=True) as ctx:
+        assert ctx.step() == 0
+        ctx.sync()
+        assert (whole_loop_launches(ctx) > 0) == persistent
+        psi = ctx.get_psi(0)
+        assert np.abs(ref["y"]).max() > 1e-3
+        assert relerr(psi, ref["y"]) < 1e-10
+        assert ctx.marginal(0) == pytest.approx(ref["P"], rel=1e-9)
