@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(RED_THREADS) xspace_diag_kernel(RedArgs a) {
 // stage inputs of the group's V solves are read and multiplied by alpha.eps
 // once, then each U solve is read once and dotted with them for its vertices.
 template <class R>
-__global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
+__global__ void __launch_bounds__(RED_THREADS) __attribute__((amdgpu_waves_per_eu(2, 8))) bw_stage_kernel(BwArgs a) {
     using C = cpx<R>;
     const VertexGroupDev G = a.groups[blockIdx.y];
     const int role = a.stage == 0 ? BUF_Y : BUF_YS;
@@ -231,6 +231,23 @@ __global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
         sincos(-a.solves[G.sv[u < G.nv ? u : 0]].E * ts, &sn, &cs);
         ev[u] = d2(cs, sn);
     }
+    // constant spinors of the background terms, in LDS (broadcast reads):
+    // (alpha.eps) v of each V solve, u of each U solve (the plane-wave factors
+    // are applied per site)
+    __shared__ double2 cv[BWG_SOLVES][4], cu[BWG_SOLVES][4];
+    if (threadIdx.x < BWG_SOLVES) {
+        const int u = threadIdx.x;
+        const SolveDev* SV = a.solves + G.sv[u < G.nv ? u : 0];
+        const SolveDev* SU = a.solves + G.su[u < G.nu ? u : 0];
+        double2 wv[4], gw[4];
+        for (int q = 0; q < 4; ++q) {
+            wv[q] = d2(SV->w[2 * q], SV->w[2 * q + 1]);
+            cu[u][q] = d2(SU->w[2 * q], SU->w[2 * q + 1]);
+        }
+        gam_eps(wv, gw, eps);
+        for (int q = 0; q < 4; ++q) cv[u][q] = gw[q];
+    }
+    __syncthreads();
     double acc[BWG_VERTS][3][2];
 #pragma unroll
     for (int j = 0; j < BWG_VERTS; ++j)
@@ -240,54 +257,56 @@ __global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
         const int x = (int)(i % n0);
         const long long r = i / n0;
         const int y = (int)(r % n1), z = (int)(r / n1);
-        // V side: (alpha.eps) V_scat and (alpha.eps) V_back of each V solve
-        double2 gyv[BWG_SOLVES][4], gbv[BWG_SOLVES][4];
+        // V side: (alpha.eps) V_scat of each V solve and the plane-wave factor of its background
+        double2 gyv[BWG_SOLVES][4], pv[BWG_SOLVES];
 #pragma unroll
         for (int b = 0; b < BWG_SOLVES; ++b) {
             if (b < G.nv) {
                 const SolveDev* SV = a.solves + G.sv[b];
                 const C* W = reinterpret_cast<const C*>(SV->buf[role]);
                 const C* ph = ctab + SV->ph;
-                const double2 pv = dmul(ev[b], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
-                double2 yv[4], bv[4];
+                pv[b] = dmul(ev[b], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
+                double2 yv[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    yv[q] = todbl(W[q * ns + i]);
-                    bv[q] = dmul(d2(SV->w[2 * q], SV->w[2 * q + 1]), pv);
-                }
+                for (int q = 0; q < 4; ++q) yv[q] = todbl(W[q * ns + i]);
                 gam_eps(yv, gyv[b], eps);
-                gam_eps(bv, gbv[b], eps);
             }
         }
         const double2 pk = dmul(ek, todbl(cmul(cmul(phK[x], phK[n0 + y]), phK[n0 + n1 + z])));
         const double2 pkc = d2(pk.x, -pk.y);   // conj(U) pk = conj(U conj(pk))
-        // U side, one solve at a time, against the V side of each of its vertices
+        // U side, one solve at a time, against the V side of each of its vertices:
+        //   (s,s): sum_q conj(U_q) pk G V_q;
+        //   (b,s): conj(pu conj(pk)) sum_q conj(u_q) G V_q;
+        //   (s,b): pv sum_q conj(U_q) pk (G v)_q
 #pragma unroll
         for (int u = 0; u < BWG_SOLVES; ++u) {
             if (u < G.nu) {
                 const SolveDev* SU = a.solves + G.su[u];
                 const C* U = reinterpret_cast<const C*>(SU->buf[role]);
                 const C* ph = ctab + SU->ph;
-                const double2 pu = dmul(eu[u], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
-                double2 yu[4], bu[4];
+                const double2 au = dmul(dmul(eu[u], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z]))), pkc);
+                const double2 auc = d2(au.x, -au.y);
+                double2 yu[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    yu[q] = dmul(todbl(U[q * ns + i]), pkc);                      // the photon phase folded in
-                    bu[q] = dmul(dmul(d2(SU->w[2 * q], SU->w[2 * q + 1]), pu), pkc);
-                }
+                for (int q = 0; q < 4; ++q) yu[q] = dmul(todbl(U[q * ns + i]), pkc);
 #pragma unroll
                 for (int j = 0; j < BWG_VERTS; ++j) {
                     if (j < G.nvx && G.ui[j] == u) {
                         const int vi = G.vi[j];
-                        double2 s0 = d2(0, 0), s1 = d2(0, 0), s2 = d2(0, 0);
+                        double2 s0 = d2(0, 0), t1 = d2(0, 0), t2 = d2(0, 0);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const double2 gy = vi ? gyv[1][q] : gyv[0][q];
-                            const double2 gb = vi ? gbv[1][q] : gbv[0][q];
+                            // volatile: re-read from LDS rather than held in registers
+                            const volatile double2* pcv = &cv[vi][q];
+                            const volatile double2* pcu = &cu[u][q];
+                            const double2 gb = d2(pcv->x, pcv->y);
                             s0 = dadd(s0, dcmul(yu[q], gy));
-                            s1 = dadd(s1, dcmul(bu[q], gy));
-                            s2 = dadd(s2, dcmul(yu[q], gb));
+                            t1 = dadd(t1, dcmul(d2(pcu->x, pcu->y), gy));
+                            t2 = dadd(t2, dcmul(yu[q], gb));
                         }
+                        const double2 s1 = dmul(auc, t1);
+                        const double2 s2 = dmul(vi ? pv[1] : pv[0], t2);
                         acc[j][0][0] += s0.x; acc[j][0][1] += s0.y;
                         acc[j][1][0] += s1.x; acc[j][1][1] += s1.y;
                         acc[j][2][0] += s2.x; acc[j][2][1] += s2.y;
