@@ -28,7 +28,11 @@ strong-field processes in multidimensional background fields"):
                   (eq. (MScatScatPast) and its two single-mode partners);
                   and the section's second route, eq. (MScatScat2) and its
                   partners (partial integration in t), as an independent
-                  check of the first.
+                  check of the first; and a photon wave packet f_mu(x) =
+                  sum_m c_m eps_m e^{-i k_m x} in place of the plane wave
+                  (finite part with f in the integrand, past part summed
+                  over the packet's momentum grid), as the section's
+                  numerical approach describes.
 
 Pins (tests/test_oracle_*.py, all ``-m "not gpu"``) tie every function to
 something other than itself: Clifford algebra and spinor identities, the
@@ -36,7 +40,10 @@ closed-form pure-gauge scattered wave, the Sauter-pulse pair spectrum,
 brute-force full-wave-function evolution with scipy's DOP853, unitarity and
 orthogonality identities, charge-conjugation symmetry, RK4 convergence
 order, the exact spin structure of the BW amplitude for E(t,x) fields and
-the t_in independence of past + finite BW terms.
+the t_in independence of past + finite BW terms; for wave packets, a packet
+of one plane wave is that wave, a packet is the weighted sum of its plane
+waves, and a Gaussian packet tends to the plane wave as its momentum width
+shrinks (at order sigma^2).
 
 The absorbing-boundary mask (not part of the paper; off for every other pin
 and parity case) is pinned by a wave packet leaving the box: inside the

@@ -98,11 +98,18 @@ class Vertex:
 
     def past(self, psiU, psiV, t_in):
         """M_past for (scat,scat), (back,scat), (scat,back)."""
+        return self.past_for(psiU, psiV, t_in, self.k3, self.vx.eps)
+
+    def past_for(self, psiU, psiV, t_in, k3, eps):
+        """M_past of a plane-wave photon of 3-momentum k3 and polarisation eps."""
         U, V, lat = self.U, self.V, self.U.lat
-        k3, k0, G = self.k3, self.k0, self.G
+        k3 = np.asarray(k3, dtype=float)
+        k0 = float(np.linalg.norm(k3))
+        G = gamma_eps(eps)
+        photon_x = np.exp(1j * sum(k3[j] * lat.X[j] for j in range(lat.dim))) if lat.dim > 0 else np.ones(lat.shape)
         # (scat, scat)
         Uk = lat.fft(psiU)
-        Vk = lat.fft(psiV * self.photon_x[None])
+        Vk = lat.fft(psiV * photon_x[None])
         kU = U.kfull
         kV = [kU[j] - k3[j] for j in range(3)]
         EU = np.sqrt(1.0 + sum(a ** 2 for a in kU))
@@ -239,3 +246,59 @@ class Vertex:
         past = self.past(psiU, psiV, t_in)
         return {"finite": finite, "past": past, "terms": finite + past,
                 "total": complex(np.sum(finite + past)), "psiU": psiU, "psiV": psiV}
+
+
+class PacketVertex(Vertex):
+    """Breit-Wheeler amplitude for a photon wave packet (the BW section's
+    numerical approach, on wave packets): f_mu(x) = sum_m c_m eps_m,mu e^{-i k_m x}
+    takes the place of eps_mu e^{-ikx} in the finite-time integrand of
+    eq. (Mabfinite), so with epsilon_mu = (0, eps) the integrand is
+    Ubar_a gamma^0 (alpha.E(t,x)) V_b with E = sum_m c_m eps_m e^{-i(k0_m t - k_m.x)};
+    the past terms, eq. (MScatScatPast) and its partners, are evaluated on the
+    packet's momentum grid and summed with the weights c_m."""
+
+    def __init__(self, problem, index: int):
+        vx = problem.vertices[index]
+        if not vx.modes:
+            raise ValueError("PacketVertex needs a vertex with modes")
+        self.modes = [(np.asarray(k, dtype=float), np.asarray(e, dtype=float), complex(c)) for k, e, c in vx.modes]
+        # the base class checks the solves and trivial-axis conservation with the first mode
+        import dataclasses
+        first = dataclasses.replace(vx, k=list(self.modes[0][0]), eps=list(self.modes[0][1]), modes=[])
+        probe = dataclasses.replace(problem, vertices=[first])
+        super().__init__(probe, 0)
+        self.vx = vx
+        lat = self.U.lat
+        for k3, _, _ in self.modes:
+            for j in range(lat.dim, 3):
+                if abs(self.U.K[j] - k3[j] - self.V.K[j]) > 1e-12:
+                    raise ValueError("trivial-axis momentum conservation p + q = k violated by a mode")
+        self.mode_x = [np.exp(1j * sum(k3[j] * lat.X[j] for j in range(lat.dim))) if lat.dim > 0
+                       else np.ones(lat.shape) for k3, _, _ in self.modes]
+
+    def packet_field(self, t):
+        """E(t, x): complex polarisation 3-vector field of the packet (3, *lattice)."""
+        E = np.zeros((3,) + self.U.lat.shape, dtype=complex)
+        for (k3, e, c), ph in zip(self.modes, self.mode_x):
+            a = c * np.exp(-1j * float(np.linalg.norm(k3)) * t) * ph
+            for j in range(3):
+                E[j] = E[j] + a * e[j]
+        return E
+
+    def mdot(self, t, yU, yV):
+        lat = self.U.lat
+        E = self.packet_field(t)
+        bU = self.U.psi_back(t)
+        bV = self.V.psi_back(t)
+
+        def alpha_E(b):
+            return sum(apply(dirac.ALPHA[j].reshape((4, 4) + (1,) * lat.dim) * E[j][None, None], b)
+                       for j in range(3))
+
+        def f(a, b):
+            return lat.dV * np.sum(np.conj(a) * alpha_E(b))
+
+        return np.array([f(yU, yV), f(bU, yV), f(yU, bV)])
+
+    def past(self, psiU, psiV, t_in):
+        return sum(c * self.past_for(psiU, psiV, t_in, k3, e) for k3, e, c in self.modes)

@@ -20,7 +20,10 @@ Conventions of the descriptors (units m = c = hbar = 1, charge absorbed in A):
 * A solve is an out-state U_out(s, p) (kind 0) or V_out(s, p) (kind 1), with
   p the contravariant 3-momentum.
 * A vertex pairs one U solve and one V solve with a photon of 3-momentum k
-  (k^0 = |k|) and polarisation 3-vector eps (eps_mu = (0, eps)).
+  (k^0 = |k|) and polarisation 3-vector eps (eps_mu = (0, eps)).  With
+  ``modes`` the photon is a wave packet instead: a list of (k, eps, c)
+  plane-wave components, f_mu(x) = sum_m c_m eps_m,mu exp(-i k_m x) (k, eps
+  of the vertex are then unused).
 """
 from __future__ import annotations
 
@@ -115,6 +118,23 @@ class Vertex:
     v_solve: int
     k: List[float]
     eps: List[float]
+    modes: List[tuple] = dc_field(default_factory=list)   # wave packet: (k, eps, complex c) per component
+
+
+def gaussian_packet(k_center, eps, axis, width, n_modes, spacing):
+    """Modes of a photon wave packet Gaussian in momentum along one axis:
+    k_m = k_center + m * spacing * e_axis, m = -(n_modes//2) ... n_modes//2,
+    weights exp(-(m spacing)^2 / (2 width^2)) normalised to sum 1, one
+    polarisation for all."""
+    half = n_modes // 2
+    out = []
+    w = np.exp(-((np.arange(-half, half + 1) * spacing) ** 2) / (2.0 * width ** 2))
+    w = w / w.sum()
+    for m, c in zip(range(-half, half + 1), w):
+        k = list(map(float, k_center))
+        k[axis] += m * spacing
+        out.append((k, list(map(float, eps)), complex(c)))
+    return out
 
 
 @dataclass

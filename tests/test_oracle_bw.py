@@ -68,3 +68,71 @@ def test_partial_integration_route_matches():
     assert np.all(diffs[0] < 3e-6) and np.all(diffs[1] < 2e-7)
     ratio = diffs[0] / diffs[1]
     assert np.all((ratio > 12.0) & (ratio < 20.0)), ratio
+
+
+# ---------------------------------------------------------------- wave packets
+def _fig7_problem(modes, P=2 * np.pi * 4 / 160.0):
+    prob = W.config_bw_1d(P=P, n=128, L=160.0, dt=0.1, t_half=25.0)
+    vx = prob.vertices[0]
+    prob.vertices = [W.Vertex(vx.u_solve, vx.v_solve, vx.k, vx.eps, modes)]
+    return prob
+
+
+def _plane(prob, k, eps):
+    vx = prob.vertices[0]
+    import dataclasses
+    pw = dataclasses.replace(prob, vertices=[W.Vertex(vx.u_solve, vx.v_solve, list(k), list(eps))])
+    return bw.Vertex(pw, 0).amplitude()
+
+
+def test_packet_of_one_mode_is_the_plane_wave():
+    k, eps = [0.0, 1.2, 0.0], [-1.0, 0.0, 0.0]
+    prob = _fig7_problem([(k, eps, 1.0)])
+    a = bw.PacketVertex(prob, 0).amplitude()
+    b = _plane(prob, k, eps)
+    for part in ("finite", "past"):
+        assert np.abs(a[part] - b[part]).max() <= 1e-12 * np.abs(b[part]).max()
+
+
+def test_packet_is_the_weighted_sum_of_its_plane_waves():
+    # three components with off-lattice momenta along x (the non-trivial axis;
+    # k_y = p_y + q_y is fixed by the trivial axis), two polarisations and
+    # complex weights: the packet's finite part (one integrand with the field
+    # E(t,x)) and past part equal the weighted sums of separate plane-wave runs
+    modes = [([-0.11, 1.2, 0.0], [-1.0, 0.0, 0.0], 0.5 + 0.2j),
+             ([0.0, 1.2, 0.0], [0.0, 0.0, 1.0], -0.3 + 0.4j),
+             ([0.17, 1.2, 0.0], [-0.6, 0.0, 0.8], 0.25 - 0.1j)]
+    prob = _fig7_problem(modes)
+    a = bw.PacketVertex(prob, 0).amplitude()
+    ref = {"finite": 0, "past": 0}
+    for k, e, c in modes:
+        b = _plane(prob, k, e)
+        for part in ref:
+            ref[part] = ref[part] + c * b[part]
+    for part in ref:
+        scale = np.abs(ref[part]).max()
+        assert scale > 1e-3
+        assert np.abs(a[part] - ref[part]).max() <= 1e-10 * scale, part
+    # a wrong time phase of one component is seen
+    bad = [(k, e, c) for k, e, c in modes]
+    bad[2] = ([0.17, 1.2, 0.0], [-0.6, 0.0, 0.8], -(0.25 - 0.1j))
+    a_bad = bw.PacketVertex(_fig7_problem(bad), 0).amplitude()
+    assert np.abs(a_bad["finite"] - ref["finite"]).max() > 1e-3 * np.abs(ref["finite"]).max()
+
+
+def test_packet_plane_wave_limit():
+    # a packet Gaussian in k_x about the Fig. 7 photon, weights summing to 1:
+    # as its momentum width sigma shrinks (the packet grows in x) its
+    # amplitude tends to the plane wave's, the difference falling as sigma^2
+    # (M(k) turns on a scale of ~0.01 in k_x here: the three terms are each
+    # ~2000x the total they cancel to)
+    k, eps = [0.0, 1.2, 0.0], [-1.0, 0.0, 0.0]
+    prob = _fig7_problem([(k, eps, 1.0)])
+    M0 = _plane(prob, k, eps)["total"]
+    errs = []
+    for sigma in (0.004, 0.002):
+        modes = W.gaussian_packet(k, eps, 0, sigma, 9, sigma / 2)
+        a = bw.PacketVertex(_fig7_problem(modes), 0).amplitude()["total"]
+        errs.append(abs(a - M0) / abs(M0))
+    assert errs[0] < 0.02
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
