@@ -92,8 +92,18 @@ typedef struct { int kind; int spin; double p[3]; int grid; int field; } swf_sol
 /* Breit-Wheeler vertex: photon with 3-momentum k (k^0 = |k|) and polarisation
  * eps (epsilon_mu = (0, eps), eq. (epsParaPerp) gives the usual basis).
  * u_solve must be a U solve and v_solve a V solve on the same grid and field;
- * on trivial axes p + q = k must hold. */
-typedef struct { int u_solve, v_solve; double k[3]; double eps[3]; } swf_vertex;
+ * on trivial axes p + q = k must hold.
+ * Photon wave packet (the BW section's numerical approach): with n_modes > 0
+ * the photon is f_mu(x) = sum_m c_m eps_m,mu exp(-i k_m x) instead, f taking
+ * the place of eps_mu e^{-ikx} in the finite-time integrand of eq. (Mabfinite)
+ * and the past terms (eq. (MScatScatPast) and partners) evaluated for every
+ * k_m and summed with the weights c_m; k and eps are then unused.  modes:
+ * n_modes records of 8 doubles {k[3], eps[3], Re c, Im c}, caller-owned and
+ * copied by swf_init; every k_m must be non-zero and satisfy p + q = k_m on the
+ * trivial axes; at most SWF_MAX_MODES modes (SWF_E_ARG otherwise).  Packets do
+ * not combine with options.bw_partial (SWF_E_UNSUPPORTED). */
+#define SWF_MAX_MODES 64
+typedef struct { int u_solve, v_solve; double k[3]; double eps[3]; int n_modes; const double* modes; } swf_vertex;
 
 typedef struct {
     int prec;               /* swf_precision                                          */

@@ -185,13 +185,17 @@ struct Plan {
     std::vector<TermDev> ht;
     std::vector<VertexDev> hv;
     std::vector<swf::VertexGroupDev> hg;  // vertex groups of the stage reduction
+    std::vector<swf::ModeDev> hm;         // wave-packet components of every packet vertex
+    std::vector<std::vector<std::array<double, 8>>> vmodes;   // their host copies, per vertex
+    std::vector<int> packets;             // the wave-packet vertices
     std::vector<double> rtab;           // real tables (rounded to the state precision on upload)
     std::vector<cd> ctab;               // complex tables
     std::vector<Group> batched, single; // groups per grid / per solve
     std::vector<int2> items;
     size_t state_bytes = 0;             // all state arrays
     // arena layout (byte offsets)
-    size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_vgroups = 0, off_rtab = 0, off_ctab = 0,
+    size_t off_state = 0, off_solves = 0, off_terms = 0, off_verts = 0, off_vgroups = 0, off_modes = 0, off_packets = 0,
+           off_rtab = 0, off_ctab = 0,
            off_items = 0, off_step = 0, off_M = 0, off_part = 0, off_red = 0, off_M2 = 0, off_part2 = 0, total = 0;
     std::vector<size_t> solve_off;      // state offset of each solve (bytes from off_state)
     bool bw2 = false;                   // partial-integration BW route on
@@ -350,13 +354,37 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         const swf_solve &su = solves[V.u_solve], &sv = solves[V.v_solve];
         if (su.kind != 0 || sv.kind != 1) FAIL(SWF_E_ARG, "vertex %d: needs a U solve and a V solve", v);
         if (su.grid != sv.grid || su.field != sv.field) FAIL(SWF_E_ARG, "vertex %d: solves must share grid and field", v);
-        const double k0 = std::sqrt(V.k[0] * V.k[0] + V.k[1] * V.k[1] + V.k[2] * V.k[2]);
-        if (!(k0 > 0)) FAIL(SWF_E_ARG, "vertex %d: photon momentum must be non-zero", v);
         const swf_grid& G = P.grids[su.grid];
-        for (int j = G.dim; j < 3; ++j)
-            if (std::fabs(su.p[j] + sv.p[j] - V.k[j]) > 1e-9 * (1.0 + std::fabs(V.k[j])))
-                FAIL(SWF_E_ARG, "vertex %d: p + q != k on trivial axis %d", v, j);
+        if (V.n_modes < 0 || V.n_modes > swf::MAX_MODES || (V.n_modes > 0 && !V.modes))
+            FAIL(SWF_E_ARG, "vertex %d: n_modes must be 0..%d with a modes array", v, swf::MAX_MODES);
+        if (V.n_modes > 0 && opt->bw_partial)
+            FAIL(SWF_E_UNSUPPORTED, "vertex %d: wave packets do not combine with bw_partial", v);
+        // the photon's plane-wave components: the vertex's own, or the packet's
+        std::vector<std::array<double, 8>> ms;
+        if (V.n_modes == 0) {
+            ms.push_back({V.k[0], V.k[1], V.k[2], V.eps[0], V.eps[1], V.eps[2], 1.0, 0.0});
+        } else {
+            for (int m = 0; m < V.n_modes; ++m) {
+                std::array<double, 8> r;
+                for (int c = 0; c < 8; ++c) {
+                    r[c] = V.modes[8 * m + c];
+                    if (!std::isfinite(r[c])) FAIL(SWF_E_ARG, "vertex %d: mode %d is not finite", v, m);
+                }
+                ms.push_back(r);
+            }
+        }
+        for (size_t m = 0; m < ms.size(); ++m) {
+            const double* k = ms[m].data();
+            if (!(std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) > 0))
+                FAIL(SWF_E_ARG, "vertex %d: photon momentum must be non-zero", v);
+            for (int j = G.dim; j < 3; ++j)
+                if (std::fabs(su.p[j] + sv.p[j] - k[j]) > 1e-9 * (1.0 + std::fabs(k[j])))
+                    FAIL(SWF_E_ARG, "vertex %d: p + q != k on trivial axis %d", v, j);
+        }
         P.verts.push_back(V);
+        P.verts.back().modes = nullptr;   // the caller's array is not kept
+        P.vmodes.push_back(V.n_modes > 0 ? ms : std::vector<std::array<double, 8>>());
+        if (V.n_modes > 0) P.packets.push_back(v);
     }
 
     // ---- tables
@@ -472,6 +500,21 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < G.n[j]; ++k) ph.push_back(j < G.dim ? std::polar(1.0, V.k[j] * xcoord(G, j, k)) : cd(1.0));
         d.phk = (long long)add_c(ph);
+        d.nmodes = (int)P.vmodes[v].size();
+        d.mode0 = (int)P.hm.size();
+        for (const auto& r : P.vmodes[v]) {
+            swf::ModeDev md;
+            memset(&md, 0, sizeof(md));
+            md.k0 = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            md.c[0] = r[6];
+            md.c[1] = r[7];
+            for (int j = 0; j < 3; ++j) md.eps[j] = r[3 + j];
+            std::vector<cd> phm;
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < G.n[j]; ++k) phm.push_back(j < G.dim ? std::polar(1.0, r[j] * xcoord(G, j, k)) : cd(1.0));
+            md.phk = (long long)add_c(phm);
+            P.hm.push_back(md);
+        }
         P.hv.push_back(d);
     }
     // vertices reduced together: greedily, at most 2 U and 2 V solves and 4
@@ -483,6 +526,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         return true;
     };
     for (int v = 0; v < n_verts; ++v) {
+        if (P.verts[v].n_modes > 0) continue;   // wave packets have their own reduction
         const int su = P.verts[v].u_solve, sv = P.verts[v].v_solve;
         bool placed = false;
         for (auto& g : P.hg) {
@@ -556,6 +600,10 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     off += sizeof(VertexDev) * std::max(1, n_verts);
     P.off_vgroups = off = align256(off);
     off += sizeof(swf::VertexGroupDev) * std::max<size_t>(1, P.hg.size());
+    P.off_modes = off = align256(off);
+    off += sizeof(swf::ModeDev) * std::max<size_t>(1, P.hm.size());
+    P.off_packets = off = align256(off);
+    off += sizeof(int) * std::max<size_t>(1, P.packets.size());
     P.off_rtab = off = align256(off);
     off += P.rsize * std::max<size_t>(1, P.rtab.size());
     P.off_ctab = off = align256(off);
@@ -616,6 +664,8 @@ struct swf_ctx {
     TermDev* d_terms() { return (TermDev*)(arena + P.off_terms); }
     VertexDev* d_verts() { return (VertexDev*)(arena + P.off_verts); }
     swf::VertexGroupDev* d_vgroups() { return (swf::VertexGroupDev*)(arena + P.off_vgroups); }
+    swf::ModeDev* d_modes() { return (swf::ModeDev*)(arena + P.off_modes); }
+    int* d_packets() { return (int*)(arena + P.off_packets); }
     void* d_rtab() { return arena + P.off_rtab; }
     void* d_ctab() { return arena + P.off_ctab; }
     int2* d_items() { return (int2*)(arena + P.off_items); }
@@ -833,11 +883,16 @@ static int bw_stage(swf_ctx* ctx, int stage) {
         if (r) return r;
         HIPCHK(hipEventRecord(e0, ctx->st));
     }
-    HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.hg.size(), ctx->st));
+    b.modes = ctx->d_modes();
+    b.packets = ctx->d_packets();
+    if (!ctx->P.hg.empty()) HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.hg.size(), ctx->st));
+    if (!ctx->P.packets.empty())
+        HIPCHK(swf::launch_bw_packet_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.packets.size(), ctx->st));
     if (prof) {
-        // every state of a group's solves is read once
+        // every state of a group's solves is read once; a packet reads its two
         double bytes = 0;
         for (auto& g : ctx->P.hg) bytes += (g.nu + g.nv) * 4.0 * ctx->P.csize * (double)ctx->P.hs[g.su[0]].nsites;
+        for (int v : ctx->P.packets) bytes += 2.0 * 4.0 * ctx->P.csize * (double)ctx->P.hs[ctx->P.hv[v].su].nsites;
         HIPCHK(hipEventRecord(e1, ctx->st));
         ctx->pending.push_back({e0, e1, 3, bytes});
     }
@@ -1369,24 +1424,21 @@ static int pair_matrix(swf_ctx* ctx, int form, const std::vector<int>& us, const
 }
 
 // Breit-Wheeler amplitude terms of vertex v at t_in.
-static int bw_terms(swf_ctx* ctx, int v) {
-    if (ctx->bw_done[v]) return SWF_OK;
+// Past terms of vertex v's solves for one plane-wave photon (k, eps; phk: its
+// exp(i k.x) tables), added with weight w to out[0..2] = (scat,scat),
+// (back,scat), (scat,back).
+static int past_terms(swf_ctx* ctx, int v, const double* k, const double* eps, long long phk, cd w, cd* out) {
     const VertexDev& V = ctx->P.hv[v];
-    const swf_vertex& VX = ctx->P.verts[v];
     const int su = V.su, sv = V.sv;
     const double tin = ctx->P.win.t_in;
-    // finite parts: M(t_in) accumulated from t_out, M_finite = -M(t_in)
-    double2 M[3];
-    HIPCHK(hipMemcpyAsync(M, ctx->d_M() + 3 * v, sizeof(M), hipMemcpyDeviceToHost, ctx->st));
-    HIPCHK(hipStreamSynchronize(ctx->st));
-    for (int t = 0; t < 3; ++t) ctx->bw_cache[6 * v + t] = -cd(M[t].x, M[t].y);
+    const double k0 = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
     // (scat, scat) past term: FFT(U_s) and FFT(V_s e^{i k.x})
     int r = kspace(ctx, su);
     if (r) return r;
     {
         const Group& g = ctx->P.single[sv];
         const int dim = ctx->P.grids[g.grid].dim;
-        r = row_pass(ctx, g, swf::ROW_FWDPH, 0, swf::BUF_Y, swf::BUF_ACC, 0, V.phk);
+        r = row_pass(ctx, g, swf::ROW_FWDPH, 0, swf::BUF_Y, swf::BUF_ACC, 0, phk);
         if (!r && dim >= 2) r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_ACC);
         if (!r && dim >= 3) r = col_pass(ctx, g, 2, swf::COL_FWD, swf::BUF_ACC);
         if (r) return r;
@@ -1398,22 +1450,21 @@ static int bw_terms(swf_ctx* ctx, int v) {
     a.ra = swf::BUF_T;
     a.rb = swf::BUF_ACC;
     for (int j = 0; j < 3; ++j) {
-        a.kv[j] = VX.k[j];
-        a.eps[j] = VX.eps[j];
+        a.kv[j] = k[j];
+        a.eps[j] = eps[j];
     }
-    a.k0 = V.k0;
+    a.k0 = k0;
     std::vector<cd> o;
     r = reduce(ctx, swf::RED_KBWPAST, a, 1, o);
     if (r) return r;
     const auto& HU = ctx->P.hs[su];
-    ctx->bw_cache[6 * v + 3] = std::polar(1.0, -V.k0 * tin) * o[0] * HU.dV * HU.inv_n;
+    out[0] += w * std::polar(1.0, -k0 * tin) * o[0] * HU.dV * HU.inv_n;
     const swf_solve& SU = ctx->P.solves[su];
     const swf_solve& SV = ctx->P.solves[sv];
-    const double* eps = VX.eps;
     // (back, scat): kappa = p - k
     {
         double kap[3];
-        for (int j = 0; j < 3; ++j) kap[j] = SU.p[j] - VX.k[j];
+        for (int j = 0; j < 3; ++j) kap[j] = SU.p[j] - k[j];
         Spinor Vc;
         r = fourier_coeff(ctx, sv, kap, Vc);
         if (r) return r;
@@ -1423,14 +1474,14 @@ static int bw_terms(swf_ctx* ctx, int v) {
         cd m = 0;
         for (int sp = -1; sp <= 1; sp += 2) {
             const Spinor PV = proj(Vc, kap, sp);
-            m += dot(u, gamma_eps(PV, eps)) / cd(0.0, p0 - sp * Ek - V.k0);
+            m += dot(u, gamma_eps(PV, eps)) / cd(0.0, p0 - sp * Ek - k0);
         }
-        ctx->bw_cache[6 * v + 4] = m * std::polar(1.0, (p0 - V.k0) * tin);
+        out[1] += w * m * std::polar(1.0, (p0 - k0) * tin);
     }
     // (scat, back): kappa = k - q
     {
         double kap[3];
-        for (int j = 0; j < 3; ++j) kap[j] = VX.k[j] - SV.p[j];
+        for (int j = 0; j < 3; ++j) kap[j] = k[j] - SV.p[j];
         Spinor Uc;
         r = fourier_coeff(ctx, su, kap, Uc);
         if (r) return r;
@@ -1441,10 +1492,37 @@ static int bw_terms(swf_ctx* ctx, int v) {
         cd m = 0;
         for (int sg = -1; sg <= 1; sg += 2) {
             const Spinor PU = proj(Uc, kap, sg);
-            m += dot(PU, gv) / cd(0.0, sg * Ek + q0 - V.k0);
+            m += dot(PU, gv) / cd(0.0, sg * Ek + q0 - k0);
         }
-        ctx->bw_cache[6 * v + 5] = m * std::polar(1.0, (q0 - V.k0) * tin);
+        out[2] += w * m * std::polar(1.0, (q0 - k0) * tin);
     }
+    return SWF_OK;
+}
+
+// Breit-Wheeler amplitude terms of vertex v at t_in: the finite parts from the
+// integrated Mdot, the past parts of its photon (for a wave packet, summed over
+// its modes with their weights).
+static int bw_terms(swf_ctx* ctx, int v) {
+    if (ctx->bw_done[v]) return SWF_OK;
+    const VertexDev& V = ctx->P.hv[v];
+    const swf_vertex& VX = ctx->P.verts[v];
+    // finite parts: M(t_in) accumulated from t_out, M_finite = -M(t_in)
+    double2 M[3];
+    HIPCHK(hipMemcpyAsync(M, ctx->d_M() + 3 * v, sizeof(M), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    for (int t = 0; t < 3; ++t) ctx->bw_cache[6 * v + t] = -cd(M[t].x, M[t].y);
+    cd past[3] = {0, 0, 0};
+    int r = SWF_OK;
+    if (V.nmodes == 0 || ctx->P.vmodes[v].empty()) {
+        r = past_terms(ctx, v, VX.k, VX.eps, V.phk, cd(1.0), past);
+    } else {
+        for (int m = 0; m < V.nmodes && !r; ++m) {
+            const auto& md = ctx->P.vmodes[v][m];
+            r = past_terms(ctx, v, md.data(), md.data() + 3, ctx->P.hm[V.mode0 + m].phk, cd(md[6], md[7]), past);
+        }
+    }
+    if (r) return r;
+    for (int t = 0; t < 3; ++t) ctx->bw_cache[6 * v + 3 + t] = past[t];
     ctx->bw_done[v] = 1;
     return SWF_OK;
 }
@@ -1541,6 +1619,12 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         INITCHK(hipMemcpyAsync(ctx->d_verts(), P.hv.data(), sizeof(VertexDev) * P.hv.size(), hipMemcpyHostToDevice, ctx->st));
     if (!P.hg.empty())
         INITCHK(hipMemcpyAsync(ctx->d_vgroups(), P.hg.data(), sizeof(swf::VertexGroupDev) * P.hg.size(),
+                               hipMemcpyHostToDevice, ctx->st));
+    if (!P.hm.empty())
+        INITCHK(hipMemcpyAsync(ctx->d_modes(), P.hm.data(), sizeof(swf::ModeDev) * P.hm.size(), hipMemcpyHostToDevice,
+                               ctx->st));
+    if (!P.packets.empty())
+        INITCHK(hipMemcpyAsync(ctx->d_packets(), P.packets.data(), sizeof(int) * P.packets.size(),
                                hipMemcpyHostToDevice, ctx->st));
     std::vector<char> rt(P.rsize * std::max<size_t>(1, P.rtab.size())), ct(P.csize * std::max<size_t>(1, P.ctab.size()));
     for (size_t i = 0; i < P.rtab.size(); ++i) {

@@ -21,8 +21,18 @@ struct RedArgs {
     double2* out;        // per-block partials
 };
 
+// One plane-wave component of a photon wave packet.
+struct ModeDev {
+    double k0;
+    double c[2];         // weight (re, im)
+    double eps[3];
+    long long phk;       // complex offset of its exp(i k_j x_j) tables (n0 + n1 + n2 entries)
+};
+constexpr int MAX_MODES = 64;
+
 struct VertexDev {
     int su, sv;
+    int nmodes, mode0;   // wave packet: its modes (0: plane wave)
     double k0;
     double eps[3];
     long long phk;       // complex offset of exp(i k_j x_j) tables (n0 + n1 + n2 entries)
@@ -49,6 +59,8 @@ struct BwArgs {
     const SolveDev* solves;
     const VertexDev* verts;
     const VertexGroupDev* groups;   // the first route's stage reduction, one group per blockIdx.y
+    const ModeDev* modes;           // wave-packet components
+    const int* packets;             // the wave-packet vertices, one per blockIdx.y of their reduction
     const void* ctab;
     const int* step;
     double t_out, dt;
@@ -91,6 +103,7 @@ struct PairArgs {
 hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
 hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
 hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, hipStream_t st);
+hipError_t launch_bw_packet_stage(int fp64, const BwArgs& a, int blocks, int npackets, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_bw2_src(int fp64, const BwArgs& a, int blocks, hipStream_t st);
 hipError_t launch_bw2_kss(int fp64, const BwArgs& a, int blocks, hipStream_t st);

@@ -343,6 +343,93 @@ __global__ void __launch_bounds__(RED_THREADS) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// (alpha.E) p for a complex polarisation vector E (the packet's field)
+__device__ __forceinline__ void alpha_E(const double2 (&p)[4], double2 (&o)[4], const double2 (&E)[3]) {
+    const double2 em = d2(E[0].x + E[1].y, E[0].y - E[1].x);   // E_x - i E_y
+    const double2 ep = d2(E[0].x - E[1].y, E[0].y + E[1].x);   // E_x + i E_y
+    o[0] = dadd(dmul(E[2], p[2]), dmul(em, p[3]));
+    o[1] = dadd(dmul(ep, p[2]), dsc(dmul(E[2], p[3]), -1.0));
+    o[2] = dadd(dmul(E[2], p[0]), dmul(em, p[1]));
+    o[3] = dadd(dmul(ep, p[0]), dsc(dmul(E[2], p[1]), -1.0));
+}
+
+// The same integrand for a photon wave packet (one packet vertex per
+// blockIdx.y): eps_mu e^{-ikx} is replaced by the packet's field
+// E(t,x) = sum_m c_m e^{-i k0_m t} eps_m e^{i k_m.x}, assembled per site from the
+// modes' phase tables.
+template <class R>
+__global__ void __launch_bounds__(RED_THREADS) bw_packet_stage_kernel(BwArgs a) {
+    using C = cpx<R>;
+    const VertexDev* V = a.verts + a.packets[blockIdx.y];
+    const SolveDev* SU = a.solves + V->su;
+    const SolveDev* SV = a.solves + V->sv;
+    const int role = a.stage == 0 ? BUF_Y : BUF_YS;
+    const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
+    const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+    const C* ctab = reinterpret_cast<const C*>(a.ctab);
+    const int nm = V->nmodes;
+    // c_m e^{-i k0_m t} eps_m of every mode and its phase tables
+    __shared__ double2 am[MAX_MODES][3];
+    __shared__ long long phm[MAX_MODES];
+    for (int m = threadIdx.x; m < nm; m += RED_THREADS) {
+        const ModeDev* M = a.modes + V->mode0 + m;
+        double sn, cs;
+        sincos(-M->k0 * ts, &sn, &cs);
+        const double2 cm = dmul(d2(M->c[0], M->c[1]), d2(cs, sn));
+        for (int j = 0; j < 3; ++j) am[m][j] = dsc(cm, M->eps[j]);
+        phm[m] = M->phk;
+    }
+    __syncthreads();
+    double2 eu, ev;
+    {
+        double sn, cs;
+        sincos(-SU->E * ts, &sn, &cs);
+        eu = d2(cs, sn);
+        sincos(-SV->E * ts, &sn, &cs);
+        ev = d2(cs, sn);
+    }
+    const C* U = reinterpret_cast<const C*>(SU->buf[role]);
+    const C* W = reinterpret_cast<const C*>(SV->buf[role]);
+    const C* phU = ctab + SU->ph;
+    const C* phV = ctab + SV->ph;
+    const int n0 = SU->n[0], n1 = SU->n[1];
+    const long long ns = SU->nsites;
+    double2 acc[3] = {d2(0, 0), d2(0, 0), d2(0, 0)};
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
+        const int x = (int)(i % n0);
+        const long long r = i / n0;
+        const int y = (int)(r % n1), z = (int)(r / n1);
+        double2 E[3] = {d2(0, 0), d2(0, 0), d2(0, 0)};
+        for (int m = 0; m < nm; ++m) {
+            const C* t = ctab + phm[m];
+            const double2 ph = todbl(cmul(cmul(t[x], t[n0 + y]), t[n0 + n1 + z]));
+#pragma unroll
+            for (int j = 0; j < 3; ++j) E[j] = dadd(E[j], dmul(am[m][j], ph));
+        }
+        const double2 pu = dmul(eu, todbl(cmul(cmul(phU[x], phU[n0 + y]), phU[n0 + n1 + z])));
+        const double2 pv = dmul(ev, todbl(cmul(cmul(phV[x], phV[n0 + y]), phV[n0 + n1 + z])));
+        double2 yu[4], yv[4], bu[4], bv[4], gyv[4], gbv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            yu[q] = todbl(U[q * ns + i]);
+            yv[q] = todbl(W[q * ns + i]);
+            bu[q] = dmul(d2(SU->w[2 * q], SU->w[2 * q + 1]), pu);
+            bv[q] = dmul(d2(SV->w[2 * q], SV->w[2 * q + 1]), pv);
+        }
+        alpha_E(yv, gyv, E);
+        alpha_E(bv, gbv, E);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[0] = dadd(acc[0], dcmul(yu[q], gyv[q]));
+            acc[1] = dadd(acc[1], dcmul(bu[q], gyv[q]));
+            acc[2] = dadd(acc[2], dcmul(yu[q], gbv[q]));
+        }
+    }
+    // partials layout [vertex][stage][block][3]
+    double2* out = a.part + ((long long)a.packets[blockIdx.y] * 4 + a.stage) * (long long)gridDim.x * 3;
+    block_sum_store<3>(acc, out);
+}
+
 __global__ void bw_accum_kernel(BwArgs a, int nblk) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= a.nvert * 3) return;
@@ -609,6 +696,13 @@ hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, h
     dim3 g(blocks, ngroups), b(RED_THREADS);
     if (fp64) hipLaunchKernelGGL(bw_stage_kernel<double>, g, b, 0, st, a);
     else hipLaunchKernelGGL(bw_stage_kernel<float>, g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bw_packet_stage(int fp64, const BwArgs& a, int blocks, int npackets, hipStream_t st) {
+    dim3 g(blocks, npackets), b(RED_THREADS);
+    if (fp64) hipLaunchKernelGGL(bw_packet_stage_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(bw_packet_stage_kernel<float>, g, b, 0, st, a);
     return hipGetLastError();
 }
 

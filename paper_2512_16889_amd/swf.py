@@ -57,7 +57,8 @@ class Solve(C.Structure):
 
 
 class Vertex(C.Structure):
-    _fields_ = [("u_solve", C.c_int), ("v_solve", C.c_int), ("k", C.c_double * 3), ("eps", C.c_double * 3)]
+    _fields_ = [("u_solve", C.c_int), ("v_solve", C.c_int), ("k", C.c_double * 3), ("eps", C.c_double * 3),
+                ("n_modes", C.c_int), ("modes", C.POINTER(C.c_double))]
 
 
 class Options(C.Structure):
@@ -158,12 +159,23 @@ def marshal(problem):
         solves[i].grid = int(s.grid)
         solves[i].field = int(s.field)
     verts = (Vertex * max(1, len(problem.vertices)))()
+    verts.mode_arrays = []      # kept alive with the vertex array
     for i, v in enumerate(problem.vertices):
         verts[i].u_solve = int(v.u_solve)
         verts[i].v_solve = int(v.v_solve)
         for j in range(3):
             verts[i].k[j] = float(v.k[j])
             verts[i].eps[j] = float(v.eps[j])
+        modes = getattr(v, "modes", None) or []
+        verts[i].n_modes = len(modes)
+        if modes:
+            flat = []
+            for k, e, c in modes:
+                c = complex(c)
+                flat += [float(k[0]), float(k[1]), float(k[2]), float(e[0]), float(e[1]), float(e[2]), c.real, c.imag]
+            arr = (C.c_double * len(flat))(*flat)
+            verts.mode_arrays.append(arr)
+            verts[i].modes = C.cast(arr, C.POINTER(C.c_double))
     win = Window(float(problem.window.t_in), float(problem.window.t_out), float(problem.window.dt))
     return grids, terms, ffirst, solves, verts, win
 

@@ -85,3 +85,29 @@ def test_validation_errors(S):
     kinds = W.config_bw_1d(n=64, L=100.0, steps=4)
     kinds.vertices[0].u_solve, kinds.vertices[0].v_solve = 1, 0
     assert wsize(S, kinds)[0] == S.SWF_E_ARG
+
+
+def test_packet_validation(S):
+    k, eps = [0.0, 1.2, 0.0], [-1.0, 0.0, 0.0]
+
+    def packet(modes):
+        prob = W.config_bw_1d(n=64, L=100.0, steps=4)
+        vx = prob.vertices[0]
+        k0 = [0.0, vx.k[1], 0.0]
+        prob.vertices = [W.Vertex(vx.u_solve, vx.v_solve, vx.k, vx.eps, [(k0 if m[0] is None else m[0], m[1], m[2])
+                                                                         for m in modes])]
+        return prob
+    assert wsize(S, packet([(None, eps, 0.5), (None, eps, 0.5)]))[0] == 0
+    assert wsize(S, packet([(None, eps, 1.0 / 65)] * 65))[0] == S.SWF_E_ARG
+    code, _, msg = wsize(S, packet([(None, eps, 0.5), ([0.1, 0.7, 0.0], eps, 0.5)]))
+    assert code == S.SWF_E_ARG and "trivial" in msg
+    code, _, msg = wsize(S, packet([(None, eps, complex(float("nan"), 0.0))]))
+    assert code == S.SWF_E_ARG and "finite" in msg
+    code, _, msg = wsize(S, packet([(None, eps, 1.0), ([0.0, 0.0, 0.0], eps, 0.0)]))
+    assert code == S.SWF_E_ARG and "non-zero" in msg
+    grids, terms, ffirst, solves, verts, win = S.marshal(packet([(None, eps, 1.0)]))
+    opt = S.Options()
+    opt.bw_partial = 1
+    out = C.c_size_t(0)
+    assert S._lib.swf_workspace_size(grids, 1, terms, ffirst, 1, solves, 2, verts, 1, C.byref(win), C.byref(opt),
+                                     C.byref(out)) == S.SWF_E_UNSUPPORTED
