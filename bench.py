@@ -259,7 +259,7 @@ def stored_traffic(kind, precision, n, report, variant):
     elif kind == 2:
         names = [f"void swf::col_d_kernel<{real}, {n}, {variant}, 2, 1>(swf::PassArgs)"]
     else:
-        names = [f"void swf::bw_stage_kernel<{real}>(swf::BwArgs)"]
+        names = [f"void swf::bw_stage_kernel<{real}, 2, 2>(swf::BwArgs)"]
     vals = []
     for nm in names:
         k = t["kernels"].get(nm)

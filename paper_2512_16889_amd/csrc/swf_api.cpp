@@ -555,6 +555,40 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
             P.hg.push_back(g);
         }
     }
+    std::stable_sort(P.hg.begin(), P.hg.end(), [](const swf::VertexGroupDev& a, const swf::VertexGroupDev& b) {
+        return a.nu != b.nu ? a.nu < b.nu : a.nv < b.nv;
+    });
+    // per group: the constant spinors of the background terms and the spatial
+    // phase tables of its three integrands, products formed in double once
+    // (the time phases multiply the block sums)
+    for (auto& g : P.hg) {
+        const swf_vertex& V0 = P.verts[g.vtx[0]];
+        const VertexDev& D0 = P.hv[g.vtx[0]];
+        const swf_grid& G = P.grids[P.solves[g.su[0]].grid];
+        const size_t nt = (size_t)G.n[0] + G.n[1] + G.n[2];
+        for (int j = 0; j < 3; ++j) g.eps[j] = V0.eps[j];
+        g.tk = D0.phk;
+        for (int u = 0; u < g.nu; ++u) {
+            const SolveDev& S = P.hs[g.su[u]];
+            std::vector<cd> t(nt);
+            for (size_t k = 0; k < nt; ++k) t[k] = std::conj(P.ctab[S.ph + k]) * P.ctab[D0.phk + k];
+            g.t1[u] = (long long)add_c(t);
+            for (int q = 0; q < 8; ++q) g.cu[u][q] = S.w[q];
+        }
+        for (int v = 0; v < g.nv; ++v) {
+            const SolveDev& S = P.hs[g.sv[v]];
+            std::vector<cd> t(nt);
+            for (size_t k = 0; k < nt; ++k) t[k] = P.ctab[S.ph + k] * P.ctab[D0.phk + k];
+            g.t2[v] = (long long)add_c(t);
+            Spinor w;
+            for (int q = 0; q < 4; ++q) w.c[q] = cd(S.w[2 * q], S.w[2 * q + 1]);
+            const Spinor gw = gamma_eps(w, V0.eps);
+            for (int q = 0; q < 4; ++q) {
+                g.cv[v][2 * q] = gw.c[q].real();
+                g.cv[v][2 * q + 1] = gw.c[q].imag();
+            }
+        }
+    }
     // ---- groups and work items
     if (opt->chunk < 0) FAIL(SWF_E_ARG, "chunk must be >= 0");
     if (opt->check_every < 0) FAIL(SWF_E_ARG, "check_every must be >= 0");
@@ -885,7 +919,16 @@ static int bw_stage(swf_ctx* ctx, int stage) {
     }
     b.modes = ctx->d_modes();
     b.packets = ctx->d_packets();
-    if (!ctx->P.hg.empty()) HIPCHK(swf::launch_bw_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.hg.size(), ctx->st));
+    // one launch per group shape (the groups are sorted by shape)
+    const auto& hg = ctx->P.hg;
+    for (size_t g0 = 0; g0 < hg.size();) {
+        size_t g1 = g0;
+        while (g1 < hg.size() && hg[g1].nu == hg[g0].nu && hg[g1].nv == hg[g0].nv) ++g1;
+        swf::BwArgs bg = b;
+        bg.groups = ctx->d_vgroups() + g0;
+        HIPCHK(swf::launch_bw_stage(ctx->P.fp64, bg, BW_BLOCKS, hg[g0].nu, hg[g0].nv, (int)(g1 - g0), ctx->st));
+        g0 = g1;
+    }
     if (!ctx->P.packets.empty())
         HIPCHK(swf::launch_bw_packet_stage(ctx->P.fp64, b, BW_BLOCKS, (int)ctx->P.packets.size(), ctx->st));
     if (prof) {

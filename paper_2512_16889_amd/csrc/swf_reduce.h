@@ -53,6 +53,12 @@ struct VertexGroupDev {
     int su[BWG_SOLVES], sv[BWG_SOLVES];   // the solves
     int vtx[BWG_VERTS];                   // the vertices
     int ui[BWG_VERTS], vi[BWG_VERTS];     // each vertex's U and V solve within su / sv
+    double eps[3];                        // the photon's polarisation (real)
+    double cu[BWG_SOLVES][8];             // u of each U solve (re, im per component)
+    double cv[BWG_SOLVES][8];             // (alpha.eps) v of each V solve
+    long long tk;                         // exp(i k.x) tables (complex offset, n0 + n1 + n2 entries)
+    long long t1[BWG_SOLVES];             // conj(U background phase) exp(i k.x), per U solve
+    long long t2[BWG_SOLVES];             // V background phase exp(i k.x), per V solve
 };
 
 struct BwArgs {
@@ -102,7 +108,8 @@ struct PairArgs {
 
 hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
 hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
-hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, hipStream_t st);
+// a.groups: ngroups consecutive groups, all of nu U and nv V solves (1 or 2 each)
+hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int nu, int nv, int ngroups, hipStream_t st);
 hipError_t launch_bw_packet_stage(int fp64, const BwArgs& a, int blocks, int npackets, hipStream_t st);
 hipError_t launch_bw_accum(const BwArgs& a, int nblk, hipStream_t st);
 hipError_t launch_bw2_src(int fp64, const BwArgs& a, int blocks, hipStream_t st);

@@ -198,148 +198,154 @@ __global__ void __launch_bounds__(RED_THREADS) xspace_diag_kernel(RedArgs a) {
     }
 }
 
-// Breit-Wheeler integrand of eq. (Mabfinite) at one RK4 stage for every vertex:
-// Mdot_ab = sum_x e^{-i(k0 t - k.x)} Ua^dag (alpha.eps) Vb for (s,s), (b,s), (s,b).
-// One group of vertices per blockIdx.y, all with the same photon: per site the
-// stage inputs of the group's V solves are read and multiplied by alpha.eps
-// once, then each U solve is read once and dotted with them for its vertices.
-template <class R>
-__global__ void __launch_bounds__(RED_THREADS) __attribute__((amdgpu_waves_per_eu(2, 8))) bw_stage_kernel(BwArgs a) {
+// Breit-Wheeler integrand of eq. (Mabfinite) at one RK4 stage, for a group of
+// vertices with one photon and NU x NV solves (one group per blockIdx.y):
+//   Mdot_ab = sum_x e^{-i(k0 t - k.x)} Ua^dag (alpha.eps) Vb  for (s,s), (b,s), (s,b).
+// Per site the stage inputs of the V solves are read and multiplied by
+// alpha.eps once, then each U solve is read once and dotted with every V.
+// With psi_b = w e^{-iEt + iK.x} the spatial factors of the three terms are
+//   (s,s): e^{ik.x},  (b,s): conj(e^{iK_U.x}) e^{ik.x},  (s,b): e^{iK_V.x} e^{ik.x},
+// read from per-axis tables the host forms in double; the time factors
+//   e^{-ik0 t},  conj(e^{-iE_U t}) e^{-ik0 t},  e^{-iE_V t} e^{-ik0 t}
+// are constant over the sum and multiply the block sums.  Every pair (u, v) of
+// the group is summed; the vertices take theirs.  Sites are visited in a fixed
+// grid-stride order with 32-bit coordinates advanced by carries (a lattice has
+// at most 1024^3 = 2^30 sites).
+// s += conj(a) b and s += a b, four fused multiply-adds each
+__device__ __forceinline__ void cmac_conj(double2& s, double2 a, double2 b) {
+    s.x = fma(a.x, b.x, s.x);
+    s.x = fma(a.y, b.y, s.x);
+    s.y = fma(a.x, b.y, s.y);
+    s.y = fma(-a.y, b.x, s.y);
+}
+__device__ __forceinline__ void cmac(double& sx, double& sy, double2 a, double2 b) {
+    sx = fma(a.x, b.x, sx);
+    sx = fma(-a.y, b.y, sx);
+    sy = fma(a.x, b.y, sy);
+    sy = fma(a.y, b.x, sy);
+}
+// (alpha.eps) p for real eps, three fused operations per real output
+__device__ __forceinline__ void gam_eps_fma(const double2 (&p)[4], double2 (&o)[4], double e0, double e1, double e2) {
+    // rows 0, 2: e2 p_{q+2} + (e0 - i e1) p_{q+3};  rows 1, 3: (e0 + i e1) p_{q+1} - e2 p_{q+2}  (indices mod 4)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double2 a = p[2 - 2 * h], b = p[3 - 2 * h];
+        o[2 * h].x = fma(e1, b.y, fma(e0, b.x, e2 * a.x));
+        o[2 * h].y = fma(-e1, b.x, fma(e0, b.y, e2 * a.y));
+        o[2 * h + 1].x = fma(-e2, b.x, fma(-e1, a.y, e0 * a.x));
+        o[2 * h + 1].y = fma(-e2, b.y, fma(e1, a.x, e0 * a.y));
+    }
+}
+
+template <class R, int NU, int NV>
+__global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
     using C = cpx<R>;
-    const VertexGroupDev G = a.groups[blockIdx.y];
+    constexpr int NP = NU * NV;
+    const VertexGroupDev* G = a.groups + blockIdx.y;
     const int role = a.stage == 0 ? BUF_Y : BUF_YS;
-    const int n = *a.step;
-    const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
-    const double ts = a.t_out - (double)n * a.dt - cst * a.dt;
     const C* ctab = reinterpret_cast<const C*>(a.ctab);
-    const SolveDev* S0 = a.solves + G.su[0];
-    const int n0 = S0->n[0], n1 = S0->n[1];
-    const long long ns = S0->nsites;
-    const VertexDev* V0 = a.verts + G.vtx[0];
-    double snk, csk;
-    sincos(-V0->k0 * ts, &snk, &csk);
-    const double2 ek = d2(csk, snk);
-    const C* phK = ctab + V0->phk;
-    const double* eps = V0->eps;
-    // exp(-i E t) of the group's solves, once per launch
-    double2 eu[BWG_SOLVES], ev[BWG_SOLVES];
+    const SolveDev* S0 = a.solves + G->su[0];
+    const unsigned n0 = (unsigned)S0->n[0], n1 = (unsigned)S0->n[1];
+    const unsigned ns = (unsigned)S0->nsites;
+    gptr<const nv2<R>> Up[NU], Vp[NV];
+    const C* T1[NU];
+    const C* T2[NV];
 #pragma unroll
-    for (int u = 0; u < BWG_SOLVES; ++u) {
-        double sn, cs;
-        sincos(-a.solves[G.su[u < G.nu ? u : 0]].E * ts, &sn, &cs);
-        eu[u] = d2(cs, sn);
-        sincos(-a.solves[G.sv[u < G.nv ? u : 0]].E * ts, &sn, &cs);
-        ev[u] = d2(cs, sn);
+    for (int u = 0; u < NU; ++u) {
+        Up[u] = cview<R>(a.solves[G->su[u]].buf[role]);
+        T1[u] = ctab + G->t1[u];
     }
-    // constant spinors of the background terms, in LDS (broadcast reads):
-    // (alpha.eps) v of each V solve, u of each U solve (the plane-wave factors
-    // are applied per site)
-    __shared__ double2 cv[BWG_SOLVES][4], cu[BWG_SOLVES][4];
-    if (threadIdx.x < BWG_SOLVES) {
-        const int u = threadIdx.x;
-        const SolveDev* SV = a.solves + G.sv[u < G.nv ? u : 0];
-        const SolveDev* SU = a.solves + G.su[u < G.nu ? u : 0];
-        double2 wv[4], gw[4];
-        for (int q = 0; q < 4; ++q) {
-            wv[q] = d2(SV->w[2 * q], SV->w[2 * q + 1]);
-            cu[u][q] = d2(SU->w[2 * q], SU->w[2 * q + 1]);
-        }
-        gam_eps(wv, gw, eps);
-        for (int q = 0; q < 4; ++q) cv[u][q] = gw[q];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        Vp[v] = cview<R>(a.solves[G->sv[v]].buf[role]);
+        T2[v] = ctab + G->t2[v];
     }
-    __syncthreads();
-    double acc[BWG_VERTS][3][2];
+    const C* TK = ctab + G->tk;
+    const double e0 = G->eps[0], e1 = G->eps[1], e2 = G->eps[2];
+    double acc[NP][3][2];
 #pragma unroll
-    for (int j = 0; j < BWG_VERTS; ++j)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[j][c][0] = acc[j][c][1] = 0.0;
-    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < ns; i += (long long)gridDim.x * RED_THREADS) {
-        const int x = (int)(i % n0);
-        const long long r = i / n0;
-        const int y = (int)(r % n1), z = (int)(r / n1);
-        // V side: (alpha.eps) V_scat of each V solve and the plane-wave factor of its background
-        double2 gyv[BWG_SOLVES][4], pv[BWG_SOLVES];
+        for (int c = 0; c < 3; ++c) acc[p][c][0] = acc[p][c][1] = 0.0;
+    const unsigned stride = gridDim.x * RED_THREADS;
+    unsigned i = blockIdx.x * RED_THREADS + threadIdx.x;
+    unsigned x = i % n0, y = (i / n0) % n1, z = (i / n0) / n1;
+    const unsigned sx = stride % n0, sy = (stride / n0) % n1, sz = (stride / n0) / n1;
+    for (; i < ns; i += stride) {
+        const unsigned iy = n0 + y, iz = n0 + n1 + z;
+        // V side: (alpha.eps) V_scat of each V solve, and its (s,b) factor
+        double2 gy[NV][4], f2[NV];
 #pragma unroll
-        for (int b = 0; b < BWG_SOLVES; ++b) {
-            if (b < G.nv) {
-                const SolveDev* SV = a.solves + G.sv[b];
-                const C* W = reinterpret_cast<const C*>(SV->buf[role]);
-                const C* ph = ctab + SV->ph;
-                pv[b] = dmul(ev[b], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z])));
-                double2 yv[4];
+        for (int v = 0; v < NV; ++v) {
+            double2 yv[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) yv[q] = todbl(W[q * ns + i]);
-                gam_eps(yv, gyv[b], eps);
-            }
+            for (int q = 0; q < 4; ++q) yv[q] = todbl(gload_nt<C>(Vp[v], (long long)q * ns + i));
+            gam_eps_fma(yv, gy[v], e0, e1, e2);
+            f2[v] = todbl(cmul(cmul(T2[v][x], T2[v][iy]), T2[v][iz]));
         }
-        const double2 pk = dmul(ek, todbl(cmul(cmul(phK[x], phK[n0 + y]), phK[n0 + n1 + z])));
-        const double2 pkc = d2(pk.x, -pk.y);   // conj(U) pk = conj(U conj(pk))
-        // U side, one solve at a time, against the V side of each of its vertices:
-        //   (s,s): sum_q conj(U_q) pk G V_q;
-        //   (b,s): conj(pu conj(pk)) sum_q conj(u_q) G V_q;
-        //   (s,b): pv sum_q conj(U_q) pk (G v)_q
+        const double2 f0 = todbl(cmul(cmul(TK[x], TK[iy]), TK[iz]));
 #pragma unroll
-        for (int u = 0; u < BWG_SOLVES; ++u) {
-            if (u < G.nu) {
-                const SolveDev* SU = a.solves + G.su[u];
-                const C* U = reinterpret_cast<const C*>(SU->buf[role]);
-                const C* ph = ctab + SU->ph;
-                const double2 au = dmul(dmul(eu[u], todbl(cmul(cmul(ph[x], ph[n0 + y]), ph[n0 + n1 + z]))), pkc);
-                const double2 auc = d2(au.x, -au.y);
-                double2 yu[4];
+        for (int u = 0; u < NU; ++u) {
+            double2 yu[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) yu[q] = dmul(todbl(U[q * ns + i]), pkc);
+            for (int q = 0; q < 4; ++q) yu[q] = todbl(gload_nt<C>(Up[u], (long long)q * ns + i));
+            const double2 f1 = todbl(cmul(cmul(T1[u][x], T1[u][iy]), T1[u][iz]));
 #pragma unroll
-                for (int j = 0; j < BWG_VERTS; ++j) {
-                    if (j < G.nvx && G.ui[j] == u) {
-                        const int vi = G.vi[j];
-                        double2 s0 = d2(0, 0), t1 = d2(0, 0), t2 = d2(0, 0);
+            for (int v = 0; v < NV; ++v) {
+                double2 ss = d2(0, 0), bs = d2(0, 0), sb = d2(0, 0);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const double2 gy = vi ? gyv[1][q] : gyv[0][q];
-                            // volatile: re-read from LDS rather than held in registers
-                            const volatile double2* pcv = &cv[vi][q];
-                            const volatile double2* pcu = &cu[u][q];
-                            const double2 gb = d2(pcv->x, pcv->y);
-                            s0 = dadd(s0, dcmul(yu[q], gy));
-                            t1 = dadd(t1, dcmul(d2(pcu->x, pcu->y), gy));
-                            t2 = dadd(t2, dcmul(yu[q], gb));
-                        }
-                        const double2 s1 = dmul(auc, t1);
-                        const double2 s2 = dmul(vi ? pv[1] : pv[0], t2);
-                        acc[j][0][0] += s0.x; acc[j][0][1] += s0.y;
-                        acc[j][1][0] += s1.x; acc[j][1][1] += s1.y;
-                        acc[j][2][0] += s2.x; acc[j][2][1] += s2.y;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    cmac_conj(ss, yu[q], gy[v][q]);
+                    cmac_conj(bs, d2(G->cu[u][2 * q], G->cu[u][2 * q + 1]), gy[v][q]);
+                    cmac_conj(sb, yu[q], d2(G->cv[v][2 * q], G->cv[v][2 * q + 1]));
                 }
+                double (&A)[3][2] = acc[u * NV + v];
+                cmac(A[0][0], A[0][1], f0, ss);
+                cmac(A[1][0], A[1][1], f1, bs);
+                cmac(A[2][0], A[2][1], f2[v], sb);
             }
         }
+        x += sx;
+        y += sy;
+        z += sz;
+        if (x >= n0) { x -= n0; ++y; }
+        if (y >= n1) { y -= n1; ++z; }
     }
-    // block sums of the 3 terms of every vertex: a fixed butterfly within each
-    // wave, then the waves in order; partials layout [vertex][stage][block][3]
-    constexpr int NV = 3 * BWG_VERTS;
+    // block sums of the 3 terms of every pair: a fixed butterfly within each
+    // wave, then the waves in order; times the terms' time factors; partials
+    // layout [vertex][stage][block][3]
+    constexpr int NT = 3 * NP;
     constexpr int NW = RED_THREADS / 64;
-    __shared__ double2 shw[NW][NV];
+    __shared__ double2 shw[NW][NT];
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
 #pragma unroll
-    for (int j = 0; j < BWG_VERTS; ++j)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double2 v = d2(acc[j][c][0], acc[j][c][1]);
+            double2 s = d2(acc[p][c][0], acc[p][c][1]);
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
-                v.x += __shfl_down(v.x, off, 64);
-                v.y += __shfl_down(v.y, off, 64);
+                s.x += __shfl_down(s.x, off, 64);
+                s.y += __shfl_down(s.y, off, 64);
             }
-            if (lane == 0) shw[wave][3 * j + c] = v;
+            if (lane == 0) shw[wave][3 * p + c] = s;
         }
     __syncthreads();
-    if (tid < 3 * G.nvx) {
-        double2 v = shw[0][tid];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) v = dadd(v, shw[w][tid]);
+    if (tid < 3 * G->nvx) {
         const int j = tid / 3, c = tid % 3;
-        a.part[(((long long)G.vtx[j] * 4 + a.stage) * gridDim.x + blockIdx.x) * 3 + c] = v;
+        const int p = G->ui[j] * NV + G->vi[j];
+        double2 s = shw[0][3 * p + c];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s = dadd(s, shw[w][3 * p + c]);
+        const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
+        const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+        // phase of the term: -(k0 + [E_V]) t for (s,s) / (s,b), (E_U - k0) t for (b,s)
+        double w = -a.verts[G->vtx[0]].k0;
+        if (c == 1) w += a.solves[G->su[G->ui[j]]].E;
+        if (c == 2) w -= a.solves[G->sv[G->vi[j]]].E;
+        double sn, cs;
+        sincos(w * ts, &sn, &cs);
+        a.part[(((long long)G->vtx[j] * 4 + a.stage) * gridDim.x + blockIdx.x) * 3 + c] = dmul(d2(cs, sn), s);
     }
 }
 
@@ -692,11 +698,20 @@ hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hi
     return fp64 ? launch_red<double>(kind, a, blocks, st) : launch_red<float>(kind, a, blocks, st);
 }
 
-hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int ngroups, hipStream_t st) {
-    dim3 g(blocks, ngroups), b(RED_THREADS);
-    if (fp64) hipLaunchKernelGGL(bw_stage_kernel<double>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(bw_stage_kernel<float>, g, b, 0, st, a);
+template <class R>
+static hipError_t bw_stage_shape(const BwArgs& a, dim3 g, int nu, int nv, hipStream_t st) {
+    dim3 b(RED_THREADS);
+    if (nu == 1 && nv == 1) hipLaunchKernelGGL((bw_stage_kernel<R, 1, 1>), g, b, 0, st, a);
+    else if (nu == 1 && nv == 2) hipLaunchKernelGGL((bw_stage_kernel<R, 1, 2>), g, b, 0, st, a);
+    else if (nu == 2 && nv == 1) hipLaunchKernelGGL((bw_stage_kernel<R, 2, 1>), g, b, 0, st, a);
+    else if (nu == 2 && nv == 2) hipLaunchKernelGGL((bw_stage_kernel<R, 2, 2>), g, b, 0, st, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_bw_stage(int fp64, const BwArgs& a, int blocks, int nu, int nv, int ngroups, hipStream_t st) {
+    const dim3 g(blocks, ngroups);
+    return fp64 ? bw_stage_shape<double>(a, g, nu, nv, st) : bw_stage_shape<float>(a, g, nu, nv, st);
 }
 
 hipError_t launch_bw_packet_stage(int fp64, const BwArgs& a, int blocks, int npackets, hipStream_t st) {
