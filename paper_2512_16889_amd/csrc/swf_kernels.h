@@ -148,11 +148,10 @@ template <class C> __device__ __forceinline__ void gstore(gptr<nv2<decltype(C::x
     v.y = c.y;
     p[i] = v;
 }
-// streaming (non-temporal) load and store for the row pass: it reads and
-// writes each line once per launch, and nothing touches the line again before
-// the whole batch has been swept, so caching it only evicts other data.  (The
-// column pass keeps ordinary accesses: tiles that share 128-byte lines meet
-// in L2.)
+// streaming (non-temporal) load and store for the stepping passes: they read
+// and write each line once per launch, and nothing touches the line again
+// before the whole batch has been swept, so caching it only evicts other data
+// (the column tiles cover whole 128-byte lines).
 template <class C> __device__ __forceinline__ C gload_nt(gptr<const nv2<decltype(C::x)>> p, long long i) {
     const nv2<decltype(C::x)> v = __builtin_nontemporal_load(&p[i]);
     return cmake<C>(v.x, v.y);
@@ -473,12 +472,12 @@ __global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassAr
     {
         gptr<const nv2<R>> p = cview<R>(S->buf[a.src]) + base + src * ns;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[0][m] = gload<C>(p, (long long)(T * m) * stride);
+        for (int m = 0; m < E; ++m) v[0][m] = gload_nt<C>(p, (long long)(T * m) * stride);
         if constexpr (ACCUM) {
             // the partial sum of the earlier axis, loaded ahead of the transforms
             gptr<const nv2<R>> pg = cview<R>(S->buf[a.dst]) + base + q * ns;
 #pragma unroll
-            for (int m = 0; m < E; ++m) g[m] = gload<C>(pg, (long long)(T * m) * stride);
+            for (int m = 0; m < E; ++m) g[m] = gload_nt<C>(pg, (long long)(T * m) * stride);
         }
     }
     fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
@@ -494,7 +493,7 @@ __global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassAr
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
-            gstore<C>(p, (long long)(T * m) * stride, o);
+            gstore_nt<C>(p, (long long)(T * m) * stride, o);
         }
     }
 }
