@@ -17,9 +17,11 @@ strong-field processes in multidimensional background fields"):
                   paper's single/double-peak examples, eqs. (singleE), (doubleE).
 * ``swf``         the inhomogeneous Dirac equation for the scattered wave,
                   eq. (scatDirac), discretised pseudo-spectrally in space and
-                  integrated from t_out back to t_in with classical RK4.
-* ``observables`` inner products at t_in: the pair amplitude of eq. (Nmn)
-                  in both of its forms, electron/positron marginals,
+                  integrated with classical RK4 from t_out back to t_in
+                  (out-states U_out, V_out) or from t_in forward to t_out
+                  (in-states U_in, V_in).
+* ``observables`` inner products at the end of a run: the pair amplitude of
+                  eq. (Nmn) in both of its forms, electron/positron marginals,
                   norm/orthogonality diagnostics.
 * ``bw``          nonlinear Breit-Wheeler amplitude: the finite-time vertex
                   overlap of eq. (Mabfinite) integrated as an augmented
@@ -39,7 +41,10 @@ something other than itself: Clifford algebra and spinor identities, the
 closed-form pure-gauge scattered wave, the Sauter-pulse pair spectrum,
 brute-force full-wave-function evolution with scipy's DOP853, unitarity and
 orthogonality identities, charge-conjugation symmetry, RK4 convergence
-order, the exact spin structure of the BW amplitude for E(t,x) fields and
+order; for in-states, the pure-gauge closed form, the time independence of
+in/out overlaps (an in-state read at t_out against an out-state read at
+t_in) and the in/out balance of marginals over a complete lattice; the
+exact spin structure of the BW amplitude for E(t,x) fields and
 the t_in independence of past + finite BW terms; for wave packets, a packet
 of one plane wave is that wave, a packet is the weighted sum of its plane
 waves, and a Gaussian packet tends to the plane wave as its momentum width

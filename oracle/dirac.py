@@ -87,8 +87,9 @@ def polarization_basis(e, k):
 
 def background_spinor(kind: int, spin: int, p3):
     """(spinor, E, K) of the background wave w exp(-i E t + i K.x):
-    U: u_s(p) exp(-i p.x) -> (u, +p^0, +p);  V: v_s(p) exp(+i p.x) -> (v, -p^0, -p)."""
+    U: u_s(p) exp(-i p.x) -> (u, +p^0, +p);  V: v_s(p) exp(+i p.x) -> (v, -p^0, -p).
+    In- and out-states share their backgrounds (kinds 0, 2: U; 1, 3: V)."""
     p3 = np.asarray(p3, dtype=float)
-    if kind == 0:
+    if kind % 2 == 0:
         return u_spinor(spin, p3), energy(p3), p3.copy()
     return v_spinor(spin, p3), -energy(p3), -p3

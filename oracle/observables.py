@@ -15,6 +15,15 @@ makes form 1 = -form 2, so both give the same N = |Omega|^2.
 
 Electron marginal (sum over all positron states): P_e(s,p) =
 (U_scat|Pi_-|U_scat); positron marginal: P_pos(r,q) = (V_scat|Pi_+|V_scat).
+
+In-states (stepped forward from t_in) are read the same way at t_out, where
+the field is off again: the marginal of U_in is its negative-energy content
+there, and the two forms become (U_in|Pi_+|V_in) = -(U_in|Pi_-|V_in), the
+time-reversed counterpart of Omega (equal to -Omega at first order in the
+field; not the same amplitude beyond it).  The overlap of an in- and an
+out-state is time independent, which ties the two directions together:
+(U_back|V_scat^in)(t_out) = (U_scat^out|V_back)(t_in) = (U_out|V_in) and
+(U_scat^in|V_back)(t_out) = (U_back|V_scat^out)(t_in) = (U_in|V_out).
 Normalisation: dN = P d^d p / (2 pi)^d with d the number of non-trivial axes,
 per unit transverse volume.  On the lattice (psi|phi) = dV sum_x psi^dagger
 phi = dV/N sum_k psi~^dagger phi~ with psi~ = FFT(psi).
@@ -54,13 +63,13 @@ def projected_overlap(sa, psi_a, psi_b, sign: int):
 
 def marginal(sv, psi_s):
     """Electron marginal for a U solve, positron marginal for a V solve."""
-    sign = -1 if sv.solve.kind == 0 else +1
+    sign = -1 if sv.solve.kind % 2 == 0 else +1
     return float(np.real(projected_overlap(sv, psi_s, psi_s, sign)))
 
 
 def _check_pair(su, sv):
-    if su.solve.kind != 0 or sv.solve.kind != 1:
-        raise ValueError("pair amplitude needs a U solve and a V solve")
+    if su.solve.kind % 2 != 0 or sv.solve.kind % 2 != 1 or su.forward != sv.forward:
+        raise ValueError("pair amplitude needs a U solve and a V solve, both out- or both in-states")
     if su.lat.shape != sv.lat.shape or su.lat.L != sv.lat.L:
         raise ValueError("U and V must share a lattice")
     for j in range(su.lat.dim, 3):
@@ -69,13 +78,15 @@ def _check_pair(su, sv):
             raise ValueError("pair amplitude needs q_perp = -p_perp on trivial axes")
 
 
-def pair_amplitude(su, psi_u, sv, psi_v, t_in: float, form: int = 1):
-    """Omega(m, n) of eq. (Nmn) (form 1 or form 2), per (2 pi)^(3-d) delta(p_perp + q_perp)."""
+def pair_amplitude(su, psi_u, sv, psi_v, t: float, form: int = 1):
+    """Omega(m, n) of eq. (Nmn) (form 1 or form 2) from out-states at t = t_in,
+    per (2 pi)^(3-d) delta(p_perp + q_perp); for in-states at t = t_out the
+    same forms give their time-reversed counterpart."""
     _check_pair(su, sv)
     dV = su.lat.dV
     if form == 1:
-        return inner(su.psi_back(t_in), psi_v, dV) + projected_overlap(su, psi_u, psi_v, +1)
-    return inner(psi_u, sv.psi_back(t_in), dV) + projected_overlap(su, psi_u, psi_v, -1)
+        return inner(su.psi_back(t), psi_v, dV) + projected_overlap(su, psi_u, psi_v, +1)
+    return inner(psi_u, sv.psi_back(t), dV) + projected_overlap(su, psi_u, psi_v, -1)
 
 
 def pair_number(su, psi_u, sv, psi_v, t_in: float) -> float:
@@ -97,7 +108,7 @@ def marginal_in_uniform_field(sv, psi_full, A_cov):
     A_2, A_3) is still on: project with H(k) = alpha^j (k^j + A_j) + beta.
     Used for fields such as the Sauter pulse whose A does not vanish at t_in."""
     lat = sv.lat
-    sign = -1 if sv.solve.kind == 0 else +1
+    sign = -1 if sv.solve.kind % 2 == 0 else +1
     kin = [sv.kfull[j] + A_cov[j + 1] for j in range(3)]
     H = sum(dirac.ALPHA[j][:, :, None] * kin[j].reshape(1, 1, -1) for j in range(3)).reshape(
         (4, 4) + lat.shape) + dirac.BETA.reshape((4, 4) + (1,) * lat.dim)

@@ -1,19 +1,24 @@
-"""The scattered-wave-function equation, stepped from t_out back to t_in.
+"""The scattered-wave-function equation, stepped from t_out back to t_in
+(out-states) or from t_in forward to t_out (in-states).
 
 Paper, section "Scattered wave functions": psi = psi_back + psi_scat with the
-plane-wave background psi_back = u e^{-ipx} (U) or v e^{ipx} (V), and the
-scattered part solving the inhomogeneous equation (i Dslash - 1) psi_scat =
-Aslash psi_back, eq. (scatDirac), with psi_scat(t_out) = 0.  Multiplying by
-gamma^0 gives the evolution form used here,
+plane-wave background psi_back = u e^{-ipx} (U) or v e^{ipx} (V), the same for
+in- and out-states, and the scattered part solving the inhomogeneous equation
+(i Dslash - 1) psi_scat = Aslash psi_back, eq. (scatDirac), with
+psi_scat -> 0 as t -> +infinity for out-states and as t -> -infinity for
+in-states; with the field negligible outside [t_in, t_out] these are
+psi_scat(t_out) = 0 and psi_scat(t_in) = 0.  Multiplying by gamma^0 gives the
+evolution form used here,
 
     d_t psi_s = -alpha^j d_j psi_s - i beta psi_s - i (A_0 + alpha^j A_j)(psi_s + psi_b),
 
 whose kinetic part is evaluated spectrally (derivative through FFT, section
 "Numerical approach"): -i H0(k) in Fourier space with H0(k) = alpha.k + beta,
 where trivial axes contribute their conserved momentum (p_perp for U, -q_perp
-for V).  Time integration: classical RK4 with step h = -dt from t_out
-(reading of the paper's adaptive Dopri5 for the fixed-dt workloads), with
-t_n = t_out - n dt evaluated from the step index.
+for V).  Time integration: classical RK4 (reading of the paper's adaptive
+Dopri5 for the fixed-dt workloads) with step h = -dt from t_out, t_n = t_out -
+n dt, for out-states, and h = +dt from t_in, t_n = t_in + n dt, for in-states,
+the times evaluated from the step index.
 """
 from __future__ import annotations
 
@@ -30,11 +35,12 @@ def apply(M, psi):
 
 
 class SWFSolve:
-    """One out-state solve (U_out(s,p) or V_out(s,p)) on its lattice."""
+    """One solve (U_out, V_out, U_in or V_in of (s, p)) on its lattice."""
 
     def __init__(self, problem, index: int):
         sv = problem.solves[index]
         self.solve = sv
+        self.forward = sv.kind >= 2     # in-states run forward from t_in
         self.grid = problem.grids[sv.grid]
         self.terms = problem.fields[sv.field]
         self.window = problem.window
@@ -70,14 +76,22 @@ class SWFSolve:
     def rhs(self, t: float, psi):
         return self.kinetic(psi) - 1j * apply(self.potential_matrix(t), psi + self.psi_back(t))
 
-    # -- classical RK4, h = -dt -------------------------------------------
+    # -- classical RK4, h = -dt (out) or +dt (in) -------------------------
     def time(self, n: int) -> float:
+        if self.forward:
+            return self.window.t_in + n * self.window.dt
         return self.window.t_out - n * self.window.dt
+
+    @property
+    def t_end(self) -> float:
+        """Where a full run ends and the observables are read: t_in for
+        out-states, t_out for in-states."""
+        return self.window.t_out if self.forward else self.window.t_in
 
     def step_stages(self, n: int, y):
         """One RK4 step from t_n; returns y_{n+1} and the four stage inputs
         with their times (the augmented BW integral needs them)."""
-        h = -self.window.dt
+        h = self.window.dt if self.forward else -self.window.dt
         t = self.time(n)
         y1 = y
         k1 = self.rhs(t, y1)
@@ -99,8 +113,8 @@ class SWFSolve:
         return np.zeros((4,) + self.lat.shape, dtype=complex)
 
     def run(self, y=None, start: int = 0, count: int | None = None):
-        """Advance ``count`` steps from step index ``start`` (default: all the
-        way to t_in from psi_scat(t_out) = 0)."""
+        """Advance ``count`` steps from step index ``start`` (default: the
+        whole window from psi_scat = 0 at its start)."""
         if y is None:
             y = self.zero_state()
         if count is None:
@@ -111,7 +125,8 @@ class SWFSolve:
 
 
 def solve_all(problem):
-    """Run every solve of the problem to t_in; returns list of (SWFSolve, psi_s(t_in))."""
+    """Run every solve of the problem over the window; returns list of
+    (SWFSolve, psi_s at the end of its run)."""
     out = []
     for i in range(len(problem.solves)):
         s = SWFSolve(problem, i)

@@ -17,8 +17,10 @@ Conventions of the descriptors (units m = c = hbar = 1, charge absorbed in A):
 * A grid has ``dim`` non-trivial spatial axes (x; x,y; x,y,z), ``n[j]`` points
   on the periodic interval ``[-L[j]/2, L[j]/2)``.  Axes j >= dim are trivial:
   the field does not depend on them and their momentum is conserved.
-* A solve is an out-state U_out(s, p) (kind 0) or V_out(s, p) (kind 1), with
-  p the contravariant 3-momentum.
+* A solve is an out-state U_out(s, p) (kind 0) or V_out(s, p) (kind 1), or
+  an in-state U_in(s, p) (kind 2) or V_in(s, p) (kind 3), with p the
+  contravariant 3-momentum.  Out-states are stepped from t_out back to t_in
+  and read there; in-states from t_in forward to t_out and read there.
 * A vertex pairs one U solve and one V solve with a photon of 3-momentum k
   (k^0 = |k|) and polarisation 3-vector eps (eps_mu = (0, eps)).  With
   ``modes`` the photon is a wave packet instead: a list of (k, eps, c)
@@ -40,6 +42,8 @@ PROF_UGAUSS = 4  # u * exp(-u^2)
 
 U_OUT = 0
 V_OUT = 1
+U_IN = 2
+V_IN = 3
 
 
 @dataclass
