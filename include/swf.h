@@ -8,12 +8,16 @@
  *     the inhomogeneous Dirac equation (i Dslash - 1) psi_s = Aslash psi_back,
  *     eq. (scatDirac), with psi_s(t_out) = 0, where D_mu = d_mu + i A_mu and
  *     psi_back = u_s(p) e^{-ipx} or v_s(p) e^{ipx} (section "Scattered wave
- *     functions"; spinors of eq. (uv) with R_s of eq. (Reqs)).
+ *     functions"; spinors of eq. (uv) with R_s of eq. (Reqs)).  The
+ *     in-states U_in(s,p), V_in(s,p) of the same section have the same
+ *     backgrounds and psi_s(t_in) = 0.
  *   - Space is discretised pseudo-spectrally on a periodic grid (section
- *     "Numerical approach"); time is stepped with classical RK4, h = -dt,
- *     from t_out back to t_in.
- *   - At t_in the library forms the inner products of eq. (Nmn) (pair
- *     amplitude and marginals) and the Breit-Wheeler vertex amplitude
+ *     "Numerical approach"); time is stepped with classical RK4, h = -dt
+ *     from t_out back to t_in for out-states, h = +dt from t_in forward to
+ *     t_out for in-states (one direction per context).
+ *   - At the end of the run (t_in for out-states, t_out for in-states) the
+ *     library forms the inner products of eq. (Nmn) (pair amplitude and
+ *     marginals) and, for out-states, the Breit-Wheeler vertex amplitude
  *     M = M_finite + M_past of the section "Nonlinear Breit-Wheeler pair
  *     production" (eqs. (Mabfinite), (MScatScatPast) and partners).
  *
@@ -52,7 +56,7 @@ typedef enum {
                       times, field time factors and every reduction in double       */
 } swf_precision;
 
-typedef enum { SWF_U_OUT = 0, SWF_V_OUT = 1 } swf_kind;
+typedef enum { SWF_U_OUT = 0, SWF_V_OUT = 1, SWF_U_IN = 2, SWF_V_IN = 3 } swf_kind;
 
 /* Profile shapes: f(s) = env((s - c)/w) * cos(k s + phi). */
 enum {
@@ -84,9 +88,12 @@ typedef struct { int dim; int n[3]; double L[3]; int absorb_cells; double absorb
  * The field must be negligible before t_in and after t_out (eq. (Nmn) text). */
 typedef struct { double t_in, t_out, dt; } swf_window;
 
-/* One out-state solve: U_out(spin, p) (kind 0) or V_out(spin, p) (kind 1);
- * p is the contravariant 3-momentum; spin = +1 or -1 labels R_s of eq. (Reqs).
- * grid/field index the arrays given to swf_init. */
+/* One solve: U_out(spin, p) (kind 0), V_out(spin, p) (kind 1), U_in(spin, p)
+ * (kind 2) or V_in(spin, p) (kind 3) of the section "Scattered wave
+ * functions"; p is the contravariant 3-momentum; spin = +1 or -1 labels R_s of
+ * eq. (Reqs).  grid/field index the arrays given to swf_init.  The solves of a
+ * context are all out-states or all in-states (SWF_E_UNSUPPORTED otherwise):
+ * the two run in opposite time directions. */
 typedef struct { int kind; int spin; double p[3]; int grid; int field; } swf_solve;
 
 /* Breit-Wheeler vertex: photon with 3-momentum k (k^0 = |k|) and polarisation
@@ -164,8 +171,9 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms,
                     const swf_window* window, const swf_options* opt, swf_ctx** out);
 
 /* Enqueue n_steps RK4 steps of every solve (and of the BW vertex integrals)
- * toward t_in on the context's stream.  One step is classical RK4 with
- * h = -dt of eq. (scatDirac) multiplied by gamma^0 (section "Numerical
+ * toward the end of the window (t_in for out-states, t_out for in-states) on
+ * the context's stream.  One step is classical RK4 with h = -dt (out-states)
+ * or h = +dt (in-states) of eq. (scatDirac) multiplied by gamma^0 (section "Numerical
  * approach": spatial derivatives through FFTs, the vector of spinors stepped
  * in time), each BW vertex's finite-time integral, eq. (Mabfinite), carried
  * along as an extra component of the stepped state.  Asynchronous: returns
@@ -176,7 +184,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms,
  * an Inf. */
 swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left);
 
-/* Return every solve to psi_s(t_out) = 0 at step 0 and clear the BW integrals,
+/* Return every solve to psi_s = 0 at step 0 and clear the BW integrals,
  * keeping the plan, tables and captured graph (to run the same job again). */
 swf_status swf_reset(swf_ctx* ctx);
 
@@ -194,7 +202,11 @@ enum {
                               discretisation (exactly so on the lattice when p, q and k are lattice
                               momenta); an independent check of it                                 */
 };
-/* Amplitudes at t_in (requires steps_left == 0, else SWF_E_ORDER).
+/* Amplitudes at the end of the window (requires steps_left == 0, else
+ * SWF_E_ORDER): at t_in from out-states; from in-states the two PAIR forms are
+ * read at t_out, where they give (U_in|Pi_+|V_in) = -(U_in|Pi_-|V_in), the
+ * time-reversed counterpart of Omega (-Omega at first order in the field).
+ * BW: out-states only (a vertex needs a U_out and a V_out solve).
  * PAIR: coefficient of (2 pi)^(3-d) delta(p_perp + q_perp), d = dim; requires
  * q_perp = -p_perp on trivial axes (else SWF_E_ARG).  BW: M per
  * (2 pi)^(3-d) delta_perp(p + q - k), no phase-space or e^2 factors (Fig. 7). */
@@ -208,7 +220,7 @@ swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]);
  * projected one in k space), so every state is read once for the whole
  * matrix instead of once per pair; they run on the FP64 matrix cores with
  * FP64 accumulation in either precision.
- * Requirements: at t_in (SWF_E_ORDER otherwise); every u_solves[m] a U solve
+ * Requirements: at the end of the window (SWF_E_ORDER otherwise); every u_solves[m] a U solve
  * and every v_solves[n] a V solve, all on one grid, and p_perp + q_perp = 0 on
  * the trivial axes for every pair (SWF_E_ARG otherwise).  out: caller-owned,
  * 2 * nu * nv doubles.  The first call (or a larger matrix) allocates device
@@ -243,7 +255,8 @@ enum {
     SWF_P_PAIR = 2,         /* |Omega_1(i,j)|^2                                        */
     SWF_P_BW = 3            /* |M|^2 of vertex i                                       */
 };
-/* Probabilities at t_in (SWF_E_ORDER before t_in).  PAIR: the pair number
+/* Probabilities at the end of the window (SWF_E_ORDER before it; for
+ * in-states the same projections at t_out).  PAIR: the pair number
  * N = |Omega|^2 of eq. (Nmn) (form 1).  MARGINAL_E / MARGINAL_POS: the sum of
  * eq. (Nmn)'s N over every partner state, which the completeness of the free
  * states turns into the energy-projected norm of the scattered wave at t_in
@@ -252,7 +265,8 @@ enum {
  * Marginals are densities in d^d p/(2 pi)^d per unit transverse volume. */
 swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out);
 
-/* Diagnostics of solve i at the current time t = t_out - step*dt, accumulated in
+/* Diagnostics of solve i at the current time t = t_out - step*dt (out-states)
+ * or t_in + step*dt (in-states), accumulated in
  * double: out[0] = (psi_s|psi_s), out[1] = 2 Re(psi_b|psi_s) with the inner
  * product (psi|phi) = int d^3x psi^dagger phi of eq. (Nmn)'s text.  The full
  * psi = psi_b + psi_s solves the Dirac equation (eq. (scatDirac) with
@@ -280,8 +294,8 @@ swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]);
  * in over the non-trivial axes (unnormalised, numpy sign); op 1: out = the
  * kinetic term IFFT(-i H0(k) FFT(in)) of the stepper; op 2: out = the full
  * right-hand side F(t, in) at time t (kinetic + source).  in/out as swf_get_psi.
- * Uses the solve's ACC/YS/T buffers: only valid before stepping or after t_in
- * (SWF_E_ORDER otherwise). */
+ * Uses the solve's ACC/YS/T buffers: only valid before stepping or at the end
+ * of the window (SWF_E_ORDER otherwise). */
 swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in, double* out);
 
 /* Pass timing collected when options.profile = 1.  kind: 0 row pass (x axis,

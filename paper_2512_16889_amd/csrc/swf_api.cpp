@@ -3,9 +3,10 @@
 // hipGraph replay), and the host-side FP64 arithmetic of the amplitudes.
 //
 // Method: arXiv 2512.16889.  Scattered waves solve eq. (scatDirac) backward
-// from t_out; at t_in the pair amplitude (eq. (Nmn)), the marginals and the
-// Breit-Wheeler amplitude (finite part eq. (Mabfinite) + past part
-// eq. (MScatScatPast) and partners) are formed from FP64 reductions.
+// from t_out (out-states) or forward from t_in (in-states); at the end of the
+// run (t_in or t_out) the pair amplitude (eq. (Nmn)), the marginals and, for
+// out-states, the Breit-Wheeler amplitude (finite part eq. (Mabfinite) + past
+// part eq. (MScatScatPast) and partners) are formed from FP64 reductions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -181,6 +182,12 @@ struct Plan {
     std::vector<swf_solve> solves;
     std::vector<swf_vertex> verts;
     swf_window win{};
+    // direction of the time loop: out-states run from t_out back to t_in,
+    // in-states from t_in forward to t_out.  The kernels take t_n = t0 - n sdt
+    // and the step h = -sdt, so (t0, sdt) = (t_out, dt) or (t_in, -dt); the
+    // observables are read at t_obs, the end of the run.
+    bool forward = false;
+    double t0 = 0, sdt = 0, t_obs = 0;
     std::vector<SolveDev> hs;           // buf pointers filled after allocation (offsets meanwhile)
     std::vector<TermDev> ht;
     std::vector<VertexDev> hv;
@@ -280,6 +287,10 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     P.steps = (int)std::llround(span / win->dt);
     if (P.steps < 1 || std::fabs(P.steps * win->dt - span) > 1e-9 * span)
         FAIL(SWF_E_ARG, "(t_out - t_in)/dt = %.12g is not an integer step count", span / win->dt);
+    P.forward = solves[0].kind >= 2;
+    P.t0 = P.forward ? win->t_in : win->t_out;
+    P.sdt = P.forward ? -win->dt : win->dt;
+    P.t_obs = P.forward ? win->t_out : win->t_in;
     // grids
     for (int g = 0; g < n_grids; ++g) {
         swf_grid G = grids[g];
@@ -322,7 +333,9 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     // solves
     for (int i = 0; i < n_solves; ++i) {
         const swf_solve& s = solves[i];
-        if (s.kind != 0 && s.kind != 1) FAIL(SWF_E_ARG, "solve %d: kind must be 0 (U) or 1 (V)", i);
+        if (s.kind < 0 || s.kind > 3) FAIL(SWF_E_ARG, "solve %d: kind must be 0..3 (U_out, V_out, U_in, V_in)", i);
+        if ((s.kind >= 2) != (solves[0].kind >= 2))
+            FAIL(SWF_E_UNSUPPORTED, "solve %d: in- and out-states cannot share a context (opposite time directions)", i);
         if (s.spin != 1 && s.spin != -1) FAIL(SWF_E_ARG, "solve %d: spin must be +1 or -1", i);
         if (s.grid < 0 || s.grid >= n_grids) FAIL(SWF_E_ARG, "solve %d: bad grid index", i);
         if (s.field < 0 || s.field >= n_fields) FAIL(SWF_E_ARG, "solve %d: bad field index", i);
@@ -352,7 +365,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
         if (V.u_solve < 0 || V.u_solve >= n_solves || V.v_solve < 0 || V.v_solve >= n_solves)
             FAIL(SWF_E_ARG, "vertex %d: bad solve index", v);
         const swf_solve &su = solves[V.u_solve], &sv = solves[V.v_solve];
-        if (su.kind != 0 || sv.kind != 1) FAIL(SWF_E_ARG, "vertex %d: needs a U solve and a V solve", v);
+        if (su.kind != 0 || sv.kind != 1) FAIL(SWF_E_ARG, "vertex %d: needs a U_out solve and a V_out solve", v);
         if (su.grid != sv.grid || su.field != sv.field) FAIL(SWF_E_ARG, "vertex %d: solves must share grid and field", v);
         const swf_grid& G = P.grids[su.grid];
         if (V.n_modes < 0 || V.n_modes > swf::MAX_MODES || (V.n_modes > 0 && !V.modes))
@@ -437,10 +450,10 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
             d.dk[j] = 2.0 * PI / G.L[j];
         }
         d.nrows = G.n[1] * G.n[2];
-        d.kind = s.kind;
-        const double sgn = s.kind == 0 ? 1.0 : -1.0;   // K = p for U, -p for V
+        d.kind = s.kind % 2;                          // U or V (in- and out-states share the background)
+        const double sgn = d.kind == 0 ? 1.0 : -1.0;   // K = p for U, -p for V
         for (int j = 0; j < 3; ++j) d.kap[j] = j >= G.dim ? sgn * s.p[j] : 0.0;
-        Spinor w = free_spinor(s.kind, s.spin, s.p);
+        Spinor w = free_spinor(d.kind, s.spin, s.p);
         for (int q = 0; q < 4; ++q) {
             d.w[2 * q] = w.c[q].real();
             d.w[2 * q + 1] = w.c[q].imag();
@@ -777,8 +790,8 @@ static swf::PassArgs pass_args(swf_ctx* ctx) {
     a.rtab = ctx->d_rtab();
     a.ctab = ctx->d_ctab();
     a.step = ctx->d_step();
-    a.t_out = ctx->P.win.t_out;
-    a.dt = ctx->P.win.dt;
+    a.t_out = ctx->P.t0;
+    a.dt = ctx->P.sdt;
     return a;
 }
 
@@ -1299,7 +1312,7 @@ static int check_pair(swf_ctx* ctx, int i, int j) {
         ctx->err = "bad solve index";
         return SWF_E_ARG;
     }
-    if (P.solves[i].kind != 0 || P.solves[j].kind != 1) {
+    if (P.solves[i].kind % 2 != 0 || P.solves[j].kind % 2 != 1) {
         ctx->err = "pair amplitude needs a U solve (i) and a V solve (j)";
         return SWF_E_ARG;
     }
@@ -1318,7 +1331,7 @@ static int check_pair(swf_ctx* ctx, int i, int j) {
 static int pair_amp(swf_ctx* ctx, int i, int j, int form, cd& out) {
     int r = check_pair(ctx, i, j);
     if (r) return r;
-    const double tin = ctx->P.win.t_in;
+    const double tin = ctx->P.t_obs;   // t_in (out-states) or t_out (in-states)
     const auto& HU = ctx->P.hs[i];
     const auto& HV = ctx->P.hs[j];
     cd proj_term;
@@ -1404,7 +1417,7 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
             o[r].solve = rows[r];
             o[r].pad = 0;
             // background plane wave exp(i K.x): K = p for U, -q for V
-            for (int j = 0; j < 3; ++j) o[r].K[j] = sv.kind == 0 ? sv.p[j] : -sv.p[j];
+            for (int j = 0; j < 3; ++j) o[r].K[j] = sv.kind % 2 == 0 ? sv.p[j] : -sv.p[j];
         }
     };
     fill(ra, ops.data());
@@ -1454,7 +1467,7 @@ static int pair_matrix(swf_ctx* ctx, int form, const std::vector<int>& us, const
     if (form == 1) r = pair_gemm(ctx, us, swf::PG_BKG, 0, vs, swf::PG_STATE, swf::BUF_Y, 0, gx, ext, ext_bytes);
     else r = pair_gemm(ctx, us, swf::PG_STATE, swf::BUF_Y, vs, swf::PG_BKG, 0, 0, gx, ext, ext_bytes);
     if (r) return r;
-    const double tin = ctx->P.win.t_in;
+    const double tin = ctx->P.t_obs;   // t_in (out-states) or t_out (in-states)
     const double dV = ctx->P.hs[us[0]].dV, inv_n = ctx->P.hs[us[0]].inv_n;
     const size_t nu = us.size(), nv = vs.size();
     out.resize(nu * nv);
@@ -1754,7 +1767,7 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
         return SWF_E_ARG;
     }
     if (ctx->step + n_steps > ctx->P.steps) {
-        ctx->err = "swf_step past t_in";
+        ctx->err = "swf_step past the end of the window";
         return SWF_E_ORDER;
     }
     int r = enter(ctx);
@@ -1837,7 +1850,7 @@ swf_status swf_sync(swf_ctx* ctx) {
 swf_status swf_amplitude(swf_ctx* ctx, int which, int i, int j, double out[2]) {
     if (!ctx || !out) return SWF_E_ARG;
     if (ctx->step != ctx->P.steps) {
-        ctx->err = "amplitudes are defined at t_in: step to the end first";
+        ctx->err = "amplitudes are defined at the end of the window: step to the end first";
         return SWF_E_ORDER;
     }
     int r = enter(ctx);
@@ -1895,7 +1908,7 @@ static swf_status pair_matrix_abi(swf_ctx* ctx, int form, const int* u_solves, i
         return SWF_E_ARG;
     }
     if (ctx->step != ctx->P.steps) {
-        ctx->err = "amplitudes are defined at t_in: step to the end first";
+        ctx->err = "amplitudes are defined at the end of the window: step to the end first";
         return SWF_E_ORDER;
     }
     int r = enter(ctx);
@@ -1947,7 +1960,7 @@ size_t swf_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out) {
     if (!ctx || !out) return SWF_E_ARG;
     if (ctx->step != ctx->P.steps) {
-        ctx->err = "probabilities are defined at t_in: step to the end first";
+        ctx->err = "probabilities are defined at the end of the window: step to the end first";
         return SWF_E_ORDER;
     }
     if (which == SWF_P_MARGINAL_E || which == SWF_P_MARGINAL_POS) {
@@ -1956,7 +1969,7 @@ swf_status swf_probability(swf_ctx* ctx, int which, int i, int j, double* out) {
             return SWF_E_ARG;
         }
         const int want = which == SWF_P_MARGINAL_E ? 0 : 1;
-        if (ctx->P.solves[i].kind != want) {
+        if (ctx->P.solves[i].kind % 2 != want) {
             ctx->err = which == SWF_P_MARGINAL_E ? "electron marginal needs a U solve" : "positron marginal needs a V solve";
             return SWF_E_ARG;
         }
@@ -1993,9 +2006,9 @@ swf_status swf_diagnostics(swf_ctx* ctx, int i, double out[4]) {
     a.sa = i;
     a.ra = swf::BUF_Y;
     const swf_solve& s = ctx->P.solves[i];
-    const double sgn = s.kind == 0 ? 1.0 : -1.0;
+    const double sgn = s.kind % 2 == 0 ? 1.0 : -1.0;
     for (int j = 0; j < 3; ++j) a.kv[j] = sgn * s.p[j];
-    a.t = ctx->P.win.t_out - (double)ctx->step * ctx->P.win.dt;
+    a.t = ctx->P.t0 - (double)ctx->step * ctx->P.sdt;
     lattice_x(ctx, i, a);
     a.solves = ctx->d_solves();
     a.out = ctx->d_red();
@@ -2103,7 +2116,7 @@ swf_status swf_set_bw_state(swf_ctx* ctx, int i, const double in[6]) {
 swf_status swf_apply_op(swf_ctx* ctx, int op, int i, double t, const double* in, double* out) {
     if (!ctx || !in || !out || i < 0 || i >= (int)ctx->P.solves.size() || op < 0 || op > 2) return SWF_E_ARG;
     if (ctx->step != 0 && ctx->step != ctx->P.steps) {
-        ctx->err = "swf_apply_op is only valid before stepping or at t_in";
+        ctx->err = "swf_apply_op is only valid before stepping or at the end of the window";
         return SWF_E_ORDER;
     }
     int r = enter(ctx);

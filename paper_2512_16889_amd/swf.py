@@ -294,7 +294,7 @@ class Context:
 
     def marginal(self, i: int) -> float:
         kind = self.problem.solves[i].kind
-        return self.probability(P_MARGINAL_E if kind == 0 else P_MARGINAL_POS, i)
+        return self.probability(P_MARGINAL_E if kind % 2 == 0 else P_MARGINAL_POS, i)
 
     def pair(self, i: int, j: int, form: int = 1) -> complex:
         return self.amplitude(AMP_PAIR1 if form == 1 else AMP_PAIR2, i, j)

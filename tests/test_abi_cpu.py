@@ -111,3 +111,14 @@ def test_packet_validation(S):
     out = C.c_size_t(0)
     assert S._lib.swf_workspace_size(grids, 1, terms, ffirst, 1, solves, 2, verts, 1, C.byref(win), C.byref(opt),
                                      C.byref(out)) == S.SWF_E_UNSUPPORTED
+
+
+def test_in_state_validation(S):
+    prob = W.config_1d(n=64, L=100.0, steps=10)
+    prob.solves = [W.Solve(W.U_IN, 1, prob.solves[0].p), W.Solve(W.V_IN, -1, prob.solves[0].p)]
+    assert wsize(S, prob)[0] == 0
+    prob.solves[1].kind = W.V_OUT                   # opposite time directions in one context
+    code, _, msg = wsize(S, prob)
+    assert code == S.SWF_E_UNSUPPORTED and "in- and out-states" in msg
+    prob.solves[1].kind = 4
+    assert wsize(S, prob)[0] == S.SWF_E_ARG
