@@ -298,13 +298,13 @@ def _cpu_worker(name, n_cpu, solve_ids, vert_ids, steps, barrier, out_q):
     for n in range(start, start + steps):
         stages = {}
         for i, s in svs.items():
-            ys[i], st, tt = s.step_stages(n, ys[i])
+            ys[i], st, tt, _ = s.step_stages(n, ys[i])
             stages[i] = (st, tt)
             sites += s.lat.N
         for vx in verts:
             su, tt = stages[vx.vx.u_solve]
             sv, _ = stages[vx.vx.v_solve]
-            for j in range(4):
+            for j in range(len(tt)):
                 vx.mdot(tt[j], su[j], sv[j])
     out_q.put((t0, time.monotonic(), sites))
 

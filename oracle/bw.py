@@ -89,10 +89,14 @@ class Vertex:
         yV = self.V.zero_state()
         M = np.zeros(3, dtype=complex)
         for n in range(win.steps):
-            yU_new, sU, tt = self.U.step_stages(n, yU)
-            yV_new, sV, _ = self.V.step_stages(n, yV)
-            d = [self.mdot(tt[i], sU[i], sV[i]) for i in range(4)]
-            M = M + (h / 6.0) * (d[0] + 2.0 * d[1] + 2.0 * d[2] + d[3])
+            yU_new, sU, tt, wts = self.U.step_stages(n, yU)
+            yV_new, sV, _, _ = self.V.step_stages(n, yV)
+            d = [self.mdot(tt[i], sU[i], sV[i]) for i in range(len(tt))]
+            if self.U.scheme == "rk4":
+                M = M + (h / 6.0) * (d[0] + 2.0 * d[1] + 2.0 * d[2] + d[3])
+            else:
+                for w, di in zip(wts, d):
+                    M = M + (h * w) * di
             yU, yV = yU_new, yV_new
         return yU, yV, M
 
@@ -230,10 +234,14 @@ class Vertex:
         yV = self.V.zero_state()
         M = np.zeros(3, dtype=complex)
         for n in range(win.steps):
-            yU_new, sU, tt = self.U.step_stages(n, yU)
-            yV_new, sV, _ = self.V.step_stages(n, yV)
-            d = [self.mdot_partial(tt[i], sU[i], sV[i]) for i in range(4)]
-            M = M + (h / 6.0) * (d[0] + 2.0 * d[1] + 2.0 * d[2] + d[3])
+            yU_new, sU, tt, wts = self.U.step_stages(n, yU)
+            yV_new, sV, _, _ = self.V.step_stages(n, yV)
+            d = [self.mdot_partial(tt[i], sU[i], sV[i]) for i in range(len(tt))]
+            if self.U.scheme == "rk4":
+                M = M + (h / 6.0) * (d[0] + 2.0 * d[1] + 2.0 * d[2] + d[3])
+            else:
+                for w, di in zip(wts, d):
+                    M = M + (h * w) * di
             yU, yV = yU_new, yV_new
         terms = -M
         return {"terms": terms, "total": complex(np.sum(terms))}

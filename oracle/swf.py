@@ -18,7 +18,8 @@ where trivial axes contribute their conserved momentum (p_perp for U, -q_perp
 for V).  Time integration: classical RK4 (reading of the paper's adaptive
 Dopri5 for the fixed-dt workloads) with step h = -dt from t_out, t_n = t_out -
 n dt, for out-states, and h = +dt from t_in, t_n = t_in + n dt, for in-states,
-the times evaluated from the step index.
+the times evaluated from the step index; or the paper's Dopri5 (the
+Dormand-Prince 5(4) tableau) with the same fixed step (window.scheme "dp5").
 """
 from __future__ import annotations
 
@@ -27,6 +28,23 @@ import numpy as np
 from . import dirac
 from .field import potential
 from .lattice import Lattice
+
+
+# Dormand-Prince 5(4) tableau (Dormand and Prince, J. Comput. Appl. Math. 6
+# (1980) 19), the Dopri5 solver of the paper's listing in section "Numerical
+# approach", here taken with a fixed step: c, the rows of A, the fifth-order
+# weights b (b = the last row of A, so the last stage is the next step's
+# first) and the embedded fourth-order weights bhat of its error estimate.
+DP5_C = (0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0)
+DP5_A = ((),
+         (1 / 5,),
+         (3 / 40, 9 / 40),
+         (44 / 45, -56 / 15, 32 / 9),
+         (19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729),
+         (9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656),
+         (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84))
+DP5_B = (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84, 0.0)
+DP5_BHAT = (5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200, 187 / 2100, 1 / 40)
 
 
 def apply(M, psi):
@@ -41,6 +59,9 @@ class SWFSolve:
         sv = problem.solves[index]
         self.solve = sv
         self.forward = sv.kind >= 2     # in-states run forward from t_in
+        self.scheme = getattr(problem.window, "scheme", "rk4")
+        if self.scheme not in ("rk4", "dp5"):
+            raise ValueError(f"unknown time stepper {self.scheme!r}")
         self.grid = problem.grids[sv.grid]
         self.terms = problem.fields[sv.field]
         self.window = problem.window
@@ -89,8 +110,11 @@ class SWFSolve:
         return self.window.t_out if self.forward else self.window.t_in
 
     def step_stages(self, n: int, y):
-        """One RK4 step from t_n; returns y_{n+1} and the four stage inputs
-        with their times (the augmented BW integral needs them)."""
+        """One step from t_n; returns y_{n+1}, the stage inputs with their
+        times (the augmented BW integral needs them) and the scheme's weights
+        of the stages."""
+        if self.scheme == "dp5":
+            return self._dp5_stages(n, y)[:4]
         h = self.window.dt if self.forward else -self.window.dt
         t = self.time(n)
         y1 = y
@@ -104,7 +128,41 @@ class SWFSolve:
         ynew = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
         if self.mask is not None:
             ynew = ynew * self.mask[None]
-        return ynew, (y1, y2, y3, y4), (t, t + 0.5 * h, t + 0.5 * h, t + h)
+        return ynew, (y1, y2, y3, y4), (t, t + 0.5 * h, t + 0.5 * h, t + h), (1 / 6, 1 / 3, 1 / 3, 1 / 6)
+
+    # -- Dormand-Prince 5(4), fixed step ------------------------------------
+    def _dp5_stages(self, n: int, y):
+        """One Dormand-Prince step: the six stages of the fifth-order solution
+        (the seventh, at t + h with weight 0, only serves the error estimate)."""
+        h = self.window.dt if self.forward else -self.window.dt
+        t = self.time(n)
+        ys, ts, ks = [], [], []
+        for i in range(6):
+            yi = y
+            for a, k in zip(DP5_A[i], ks):
+                if a != 0.0:
+                    yi = yi + (h * a) * k
+            ti = t + DP5_C[i] * h
+            ys.append(yi)
+            ts.append(ti)
+            ks.append(self.rhs(ti, yi))
+        ynew = y
+        for b, k in zip(DP5_B, ks):
+            if b != 0.0:
+                ynew = ynew + (h * b) * k
+        if self.mask is not None:
+            ynew = ynew * self.mask[None]
+        return ynew, tuple(ys), tuple(ts), DP5_B[:6], ks, h, t
+
+    def dp5_error(self, n: int, y):
+        """(y_{n+1}, e): the step and the embedded estimate e = y5 - y4 =
+        h sum_i (b_i - bhat_i) k_i, with k_7 = F(t + h, y_{n+1}) (no mask)."""
+        if self.mask is not None:
+            raise ValueError("the error estimate is defined without the absorber")
+        ynew, _, _, _, ks, h, t = self._dp5_stages(n, y)
+        ks = ks + [self.rhs(t + h, ynew)]
+        e = sum((h * (b - bh)) * k for b, bh, k in zip(DP5_B, DP5_BHAT, ks))
+        return ynew, e
 
     def step(self, n: int, y):
         return self.step_stages(n, y)[0]

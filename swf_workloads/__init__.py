@@ -101,6 +101,7 @@ class Window:
     t_in: float
     t_out: float
     dt: float
+    scheme: str = "rk4"    # time stepper: "rk4" (classical) or "dp5" (Dormand-Prince 5, fixed step)
 
     @property
     def steps(self) -> int:
