@@ -86,7 +86,7 @@ def central_window(prob, count):
     w = prob.window
     first = (w.steps - count) // 2
     t_out = w.t_out - first * w.dt
-    return dataclasses.replace(prob, window=W.Window(t_out - count * w.dt, t_out, w.dt))
+    return dataclasses.replace(prob, window=W.Window(t_out - count * w.dt, t_out, w.dt, w.scheme))
 
 
 def components(prob):
@@ -459,6 +459,53 @@ def pair_matrix_bench(S, torch, n_each, form=1):
             "matrix_flop": flops, "sample_rel_err_vs_per_pair": err}
 
 
+def matched_error_bench(S, torch, name, n_solves=8):
+    """The two steppers at matched P error (FP64, whole window): marginals of
+    the workload's first solves from RK4 at the window's dt and at 2 dt, and
+    from the fixed-step Dormand-Prince tableau at 1, 2, 2.5 and 4 dt, each
+    against Dormand-Prince at dt/4; wall time of each whole window."""
+    import dataclasses
+    import numpy as np
+    import swf_workloads as W
+    full, desc = workload(name)
+    base = dataclasses.replace(full, solves=full.solves[:n_solves], vertices=[])
+    w = base.window
+
+    def run(scheme, f):
+        dt = w.dt * f
+        prob = dataclasses.replace(base, window=W.Window(w.t_in, w.t_out, dt, scheme))
+        with S.Context(prob, precision="fp64", tune=True, persistent=False) as ctx:
+            ctx.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.step()
+            ctx.sync()
+            wall = time.perf_counter() - t0
+            P = np.array([ctx.marginal(i) for i in range(len(prob.solves))])
+        print(f"[bench] {scheme} dt={dt:g}: {prob.window.steps} steps in {wall:.2f} s", file=sys.stderr, flush=True)
+        return P, wall, prob.window.steps
+
+    ref, _, _ = run("dp5", 0.25)
+    runs = {}
+    for scheme, fs in (("rk4", (1.0, 2.0)), ("dp5", (1.0, 2.0, 2.5, 4.0))):
+        for f in fs:
+            P, wall, steps = run(scheme, f)
+            runs[f"{scheme} dt x{f:g}"] = {"dt": w.dt * f, "steps": steps, "wall_s": wall,
+                                           "ms_per_step": wall / steps * 1e3,
+                                           "max_rel_P_err": float(np.max(np.abs(P - ref) / np.abs(ref)))}
+    target = runs["rk4 dt x1"]["max_rel_P_err"]
+    ok = [k for k, v in runs.items() if k.startswith("dp5") and v["max_rel_P_err"] <= target]
+    best = min(ok, key=lambda k: runs[k]["wall_s"]) if ok else None
+    return {"metric": "whole-window time at matched P error (Dormand-Prince vs RK4, FP64)",
+            "value": runs["rk4 dt x1"]["wall_s"] / runs[best]["wall_s"] if best else None,
+            "unit": "RK4 time / Dormand-Prince time", "n_gpus": 1, "steps": runs["rk4 dt x1"]["steps"], "warmup": 0,
+            "ms_per_step": runs["rk4 dt x1"]["ms_per_step"], "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{desc}; first {len(base.solves)} solves",
+                       "reference": "Dormand-Prince at dt/4", "rk4_error": target, "matched_by": best},
+            "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +534,11 @@ def main():
                     help="also integrate the BW vertices by the partial-integration route (timed with the steps)")
     ap.add_argument("--pair-matrix", type=int, default=0, metavar="N",
                     help="only time the N x N pair-amplitude matrix on the 2D 512^2 lattice")
+    ap.add_argument("--stepper", default="rk4", choices=["rk4", "dp5"],
+                    help="time stepper of every path (dp5: the fixed-step Dormand-Prince tableau)")
+    ap.add_argument("--matched-error", action="store_true",
+                    help="only compare the two steppers at matched P error over whole windows "
+                         "(workloads 1d, 2d, 3d; first 8 solves, FP64)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -508,6 +560,12 @@ def main():
         raise SystemExit("need --steps >= 1 and --warmup >= 0")
 
     full, desc = workload(args.workload)
+    if args.stepper != "rk4":
+        import dataclasses
+        import swf_workloads as W
+        w = full.window
+        full = dataclasses.replace(full, window=W.Window(w.t_in, w.t_out, w.dt, args.stepper))
+        desc += f"; stepper {args.stepper}"
     K, Wm = args.steps, args.warmup
     if args.full_window:
         K = full.window.steps
@@ -519,7 +577,7 @@ def main():
 
     # the CPU leg first: its worker processes start before this process touches the GPU
     cpu = None
-    if not args.no_cpu and not args.pair_matrix:
+    if not args.no_cpu and not args.pair_matrix and not args.matched_error:
         cores = len(os.sched_getaffinity(0))
         print(f"[bench] CPU baseline: oracle on up to {min(args.cpu_workers, cores)} processes", file=sys.stderr,
               flush=True)
@@ -533,6 +591,11 @@ def main():
 
     if args.pair_matrix:
         print(json.dumps(pair_matrix_bench(S, torch, args.pair_matrix)), flush=True)
+        return
+    if args.matched_error:
+        if args.workload not in ("1d", "2d", "3d"):
+            raise SystemExit("--matched-error takes the 1d, 2d or 3d workload")
+        print(json.dumps(matched_error_bench(S, torch, args.workload)), flush=True)
         return
 
     free, total = torch.cuda.mem_get_info()

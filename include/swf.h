@@ -150,7 +150,18 @@ typedef struct {
                                queued a check then waits for its work and returns
                                SWF_E_NONFINITE if one was seen (the steps are still taken;
                                swf_last_error names the step and solve).  0: no check   */
+    int stepper;            /* swf_stepper: SWF_RK4 (classical RK4, four stages, four
+                               state arrays per solve) or SWF_DP5: the Dormand-Prince
+                               5(4) tableau of the paper's Dopri5 solver (section
+                               "Numerical approach") with the fixed step dt, its
+                               fifth-order solution (six stages per step; eight state
+                               arrays per solve; no embedded error estimate or step
+                               control).  BW integrals take the tableau's weights over
+                               the stages.  SWF_DP5 does not combine with bw_partial or
+                               the persistent 1D kernel (the pass path runs instead)    */
 } swf_options;
+
+typedef enum { SWF_RK4 = 0, SWF_DP5 = 1 } swf_stepper;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */
 swf_status swf_workspace_size(const swf_grid* grids, int n_grids, const swf_term* terms,

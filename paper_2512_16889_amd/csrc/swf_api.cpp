@@ -188,6 +188,10 @@ struct Plan {
     // observables are read at t_obs, the end of the run.
     bool forward = false;
     double t0 = 0, sdt = 0, t_obs = 0;
+    // time stepper: classical RK4 (4 stages) or fixed-step Dormand-Prince 5(4) (6 stages)
+    bool dp5 = false;
+    int nst = 4;
+    double cst[6] = {}, wst[6] = {};   // stage nodes and quadrature weights
     std::vector<SolveDev> hs;           // buf pointers filled after allocation (offsets meanwhile)
     std::vector<TermDev> ht;
     std::vector<VertexDev> hv;
@@ -270,6 +274,10 @@ static void add_items(Plan& P, Group& g, int fp64) {
     if (G.dim >= 3) g.it_ocz = col_items(P, g, 2, g.k[2]->col.w, g.n_ocz);
 }
 
+// State arrays of solve i: Y, ACC, YS, T; A0, A1 for the partial-integration
+// BW route; all eight (the Dormand-Prince slopes) with that stepper.
+static int nbufs(const Plan& P, size_t i) { return P.dp5 ? swf::NBUF : (P.aux[i] ? 6 : 4); }
+
 static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_grids, const swf_term* terms,
                       const int* ffirst, int n_fields, const swf_solve* solves, int n_solves,
                       const swf_vertex* verts, int n_verts, const swf_window* win, const swf_options* opt) {
@@ -291,6 +299,14 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     P.t0 = P.forward ? win->t_in : win->t_out;
     P.sdt = P.forward ? -win->dt : win->dt;
     P.t_obs = P.forward ? win->t_out : win->t_in;
+    if (opt->stepper != SWF_RK4 && opt->stepper != SWF_DP5) FAIL(SWF_E_ARG, "stepper must be SWF_RK4 or SWF_DP5");
+    P.dp5 = opt->stepper == SWF_DP5;
+    if (P.dp5 && opt->bw_partial) FAIL(SWF_E_UNSUPPORTED, "the Dormand-Prince stepper does not combine with bw_partial");
+    P.nst = P.dp5 ? 6 : 4;
+    for (int st = 0; st < P.nst; ++st) {
+        P.cst[st] = P.dp5 ? swf::dp5_c(st) : (st == 0 ? 0.0 : st == 3 ? 1.0 : 0.5);
+        P.wst[st] = P.dp5 ? swf::dp5_a(6, st) : (st == 0 || st == 3 ? 1.0 / 6.0 : 1.0 / 3.0);
+    }
     // grids
     for (int g = 0; g < n_grids; ++g) {
         swf_grid G = grids[g];
@@ -636,7 +652,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     P.off_state = 0;
     for (int i = 0; i < n_solves; ++i) {
         P.solve_off.push_back(off);
-        off += (P.aux[i] ? 6 : 4) * align256(4 * (size_t)P.hs[i].nsites * P.csize);
+        off += (size_t)nbufs(P, i) * align256(4 * (size_t)P.hs[i].nsites * P.csize);
     }
     P.state_bytes = off;
     P.off_solves = off = align256(off);
@@ -662,7 +678,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     P.off_M = off = align256(off);
     off += sizeof(double2) * 3 * std::max(1, n_verts);
     P.off_part = off = align256(off);
-    off += sizeof(double2) * 12 * (size_t)BW_BLOCKS * std::max(1, n_verts);
+    off += sizeof(double2) * 3 * P.nst * (size_t)BW_BLOCKS * std::max(1, n_verts);
     P.off_red = off = align256(off);
     off += sizeof(double2) * 4 * (size_t)RED_BLOCKS;
     if (P.bw2) {
@@ -838,16 +854,19 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     a.h0row = ctx->P.grids[g.grid].dim == 1 ? 1 : 0;
     double trav = 2;
     if (mode == swf::ROW_STAGE) {
-        // stage input, the G buffer (2D, 3D), the RK4 operand and outputs
+        // stage input, the G buffer (2D, 3D), the RK4 operand and outputs; for
+        // Dormand-Prince also y and the earlier slopes read, the slope written
         static const double tr[4] = {2, 4, 3, 3};
-        trav = tr[stage] + (ctx->P.grids[g.grid].dim >= 2 ? 1 : 0);
+        static const double tr5[6] = {3, 5, 6, 7, 8, 7};
+        trav = (ctx->P.dp5 ? tr5[stage] : tr[stage]) + (ctx->P.grids[g.grid].dim >= 2 ? 1 : 0);
     } else if (mode == swf::ROW_RHS) {
         trav = 3;
     }
     const double bytes = trav * 4.0 * ctx->P.csize * group_sites(ctx, g);
     if (mode == swf::ROW_STAGE) {
         const auto& v = k->row[g.vr];
-        return launch(ctx, v.stage[stage], g.n_row[g.vr], g.it_row[g.vr], v.threads, v.lds, a, kind, bytes);
+        return launch(ctx, ctx->P.dp5 ? v.dp5[stage] : v.stage[stage], g.n_row[g.vr], g.it_row[g.vr], v.threads,
+                      v.lds, a, kind, bytes);
     }
     return launch(ctx, k->row_other[mode], g.n_orow, g.it_orow, k->row0_threads, k->row0_lds, a, kind, bytes);
 }
@@ -918,6 +937,8 @@ static int bw_stage(swf_ctx* ctx, int stage) {
     b.t_out = ctx->P.win.t_out;
     b.dt = ctx->P.win.dt;
     b.stage = stage;
+    b.cst = ctx->P.cst[stage];
+    b.nst = ctx->P.nst;
     b.nvert = (int)ctx->P.hv.size();
     b.part = ctx->d_part();
     b.M = ctx->d_M();
@@ -962,6 +983,8 @@ static int bw_accum(swf_ctx* ctx) {
     b.solves = ctx->d_solves();
     b.verts = ctx->d_verts();
     b.dt = ctx->P.win.dt;
+    b.nst = ctx->P.nst;
+    for (int st = 0; st < ctx->P.nst; ++st) b.wst[st] = ctx->P.wst[st];
     b.nvert = (int)ctx->P.hv.size();
     b.part = ctx->d_part();
     b.M = ctx->d_M();
@@ -1042,16 +1065,16 @@ static int bw2_accum(swf_ctx* ctx) {
 // Enqueue one full RK4 step of every solve.
 static int enqueue_step(swf_ctx* ctx) {
     if (ctx->opt.batched && ctx->opt.chunk > 0 && ctx->P.hv.empty()) {
-        // chunk-major: all four stages of one chunk before the next chunk
+        // chunk-major: all stages of one chunk before the next chunk
         for (const auto& g : groups(ctx))
-            for (int s = 0; s < 4; ++s) {
+            for (int s = 0; s < ctx->P.nst; ++s) {
                 int r = stage_passes(ctx, g, s);
                 if (r) return r;
             }
         HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
         return SWF_OK;
     }
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < ctx->P.nst; ++s) {
         int r = bw_stage(ctx, s);
         if (!r && ctx->P.bw2) r = bw2_stage(ctx, s);
         if (r) return r;
@@ -1093,7 +1116,7 @@ static int line_build(const swf_ctx* ctx, const Group& g) {
 // kernel whose LDS (with the group's field terms) fits, and no vertex couples
 // two solves.
 static bool line_path(swf_ctx* ctx) {
-    if (!ctx->opt.persistent || !ctx->P.hv.empty()) return false;
+    if (!ctx->opt.persistent || !ctx->P.hv.empty() || ctx->P.dp5) return false;
     for (const auto& g : groups(ctx))
         if (line_build(ctx, g) < 0) return false;
     return true;
@@ -1142,8 +1165,8 @@ static int build_graph(swf_ctx* ctx) {
 static std::string tune_key(swf_ctx* ctx, const Group& g) {
     const swf_grid& G = ctx->P.grids[g.grid];
     char b[160];
-    snprintf(b, sizeof(b), "deriv %s d%d n%dx%dx%d b%zu", ctx->P.fp64 ? "f64" : "f32", G.dim, G.n[0], G.n[1], G.n[2],
-             g.solves.size());
+    snprintf(b, sizeof(b), "deriv%s %s d%d n%dx%dx%d b%zu", ctx->P.dp5 ? "-dp5" : "", ctx->P.fp64 ? "f64" : "f32", G.dim,
+             G.n[0], G.n[1], G.n[2], g.solves.size());
     return b;
 }
 
@@ -1200,7 +1223,8 @@ static int autotune(swf_ctx* ctx, std::vector<Group>& gl) {
         for (int v = 0; v < g.k[0]->nvar; ++v) {
             g.vr = v;
             float ms = 0;
-            int r = time_it(ctx, [&] { return row_pass(ctx, g, swf::ROW_STAGE, 1, 0, 0, 0, 0, 4); }, reps, &ms);
+            const int st = ctx->P.dp5 ? 3 : 1;   // a middle stage of the stepper
+            int r = time_it(ctx, [&] { return row_pass(ctx, g, swf::ROW_STAGE, st, 0, 0, 0, 0, 4); }, reps, &ms);
             if (r) { ctx->opt.profile = prof; return r; }
             rep << key << ": row v" << v << " " << ms << " ms\n";
             if (ms < best) { best = ms; bv = v; }
@@ -1666,7 +1690,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
     }
     // fill buffer pointers and upload descriptors / tables
     for (size_t i = 0; i < P.hs.size(); ++i)
-        for (int role = 0; role < 6; ++role) P.hs[i].buf[role] = (role < 4 || P.aux[i]) ? ctx->buf((int)i, role) : nullptr;
+        for (int role = 0; role < swf::NBUF; ++role) P.hs[i].buf[role] = role < nbufs(P, i) ? ctx->buf((int)i, role) : nullptr;
     INITCHK(hipMemsetAsync(ctx->arena + P.off_state, 0, P.state_bytes, ctx->st));
     INITCHK(hipMemcpyAsync(ctx->d_solves(), P.hs.data(), sizeof(SolveDev) * P.hs.size(), hipMemcpyHostToDevice, ctx->st));
     if (!P.ht.empty())
@@ -1731,6 +1755,8 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 for (int v = 0; v < swf::NVAR; ++v) {
                     for (int st = 0; st < 4; ++st)
                         INITCHK(hipFuncSetAttribute(k->row[v].stage[st], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
+                    for (int st = 0; st < 6; ++st)
+                        INITCHK(hipFuncSetAttribute(k->row[v].dp5[st], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->row[v].lds));
                     for (int a = 0; a < 2; ++a)
                         for (int m = 0; m < 2; ++m)
                             INITCHK(hipFuncSetAttribute(k->cd[v].fn[a][m], hipFuncAttributeMaxDynamicSharedMemorySize, (int)k->cd[v].lds));

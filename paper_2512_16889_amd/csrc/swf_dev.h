@@ -49,8 +49,10 @@ struct TermDev {
 
 // Everything a kernel needs to know about one solve.
 struct SolveDev {
-    void* buf[6];         // state arrays: Y (psi_s), ACC (RK accumulator), YS (stage input), T (FFT work);
-                          // A0, A1: transforms of the partial-integration BW route (NULL unless used)
+    void* buf[8];         // state arrays: Y (psi_s), ACC (RK accumulator), YS (stage input), T (FFT work);
+                          // A0, A1: transforms of the partial-integration BW route; with the
+                          // Dormand-Prince stepper ACC, A0, A1, K3, K4 hold its stage slopes k_0..k_4
+                          // (NULL where unused)
     int dim;
     int n[3];
     long long nsites;     // n0 * n1 * n2
@@ -68,7 +70,32 @@ struct SolveDev {
     long long tw[3];      // offset (complex) of the twiddle table of each axis' length
 };
 
-enum { BUF_Y = 0, BUF_ACC = 1, BUF_YS = 2, BUF_T = 3, BUF_A0 = 4, BUF_A1 = 5 };
+enum { BUF_Y = 0, BUF_ACC = 1, BUF_YS = 2, BUF_T = 3, BUF_A0 = 4, BUF_A1 = 5, BUF_K3 = 6, BUF_K4 = 7 };
+constexpr int NBUF = 8;
+
+// Dormand-Prince 5(4) tableau (Dormand and Prince 1980; the Dopri5 of the
+// paper's listing), fixed step: stage nodes c_s and the coefficients a_ij of
+// the stage inputs y_i = y + h sum_j a_ij k_j, with row 6 the fifth-order
+// weights b (b_6 = 0: the last row's slope serves only the error estimate,
+// which is not formed).  The slopes k_0..k_4 live in these state arrays.
+__host__ __device__ constexpr double dp5_c(int s) {
+    return s == 0 ? 0.0 : s == 1 ? 0.2 : s == 2 ? 0.3 : s == 3 ? 0.8 : s == 4 ? 8.0 / 9.0 : 1.0;
+}
+__host__ __device__ constexpr double dp5_a(int i, int j) {
+    return i == 1 ? (j == 0 ? 0.2 : 0.0)
+         : i == 2 ? (j == 0 ? 3.0 / 40 : j == 1 ? 9.0 / 40 : 0.0)
+         : i == 3 ? (j == 0 ? 44.0 / 45 : j == 1 ? -56.0 / 15 : j == 2 ? 32.0 / 9 : 0.0)
+         : i == 4 ? (j == 0 ? 19372.0 / 6561 : j == 1 ? -25360.0 / 2187 : j == 2 ? 64448.0 / 6561
+                     : j == 3 ? -212.0 / 729 : 0.0)
+         : i == 5 ? (j == 0 ? 9017.0 / 3168 : j == 1 ? -355.0 / 33 : j == 2 ? 46732.0 / 5247 : j == 3 ? 49.0 / 176
+                     : j == 4 ? -5103.0 / 18656 : 0.0)
+         : i == 6 ? (j == 0 ? 35.0 / 384 : j == 2 ? 500.0 / 1113 : j == 3 ? 125.0 / 192 : j == 4 ? -2187.0 / 6784
+                     : j == 5 ? 11.0 / 84 : 0.0)
+         : 0.0;
+}
+__host__ __device__ constexpr int dp5_kbuf(int j) {   // the array holding slope k_j
+    return j == 0 ? BUF_ACC : j == 1 ? BUF_A0 : j == 2 ? BUF_A1 : j == 3 ? BUF_K3 : BUF_K4;
+}
 
 // ---------------------------------------------------------------- FFT plans
 template <int N> struct FftPlan;

@@ -508,7 +508,10 @@ __global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassAr
 //     k_q = -i [alpha^1 D_x y + G + (beta y) + sum over trivial axes kappa_j (alpha^j y)
 //               + (A_0 + alpha^j A_j)(y + psi_b)]_q,
 // the RK4 update of component q with the accumulator written once, and the
-// absorber at the last stage.
+// absorber at the last stage.  STAGE 4..9 are the six stages of the
+// fixed-step Dormand-Prince 5(4) stepper instead: the stage writes its slope
+// k_s and the next stage input y + h sum_{j<=s} a_{s+1,j} k_j (reading the
+// earlier slopes), the last one the step y + h sum_j b_j k_j.
 //   v0 / v1: few-points plan, 256 / 128 threads per block;
 //   v2 / v3 (SITE): few-points / default plan, 256 / 128 threads: the thread
 //   reads component 3 - q of the stage input for the transform straight from
@@ -571,7 +574,11 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
     const int n0 = S->n[0], n1 = S->n[1];
     const int yy = rowc % n1, zz = rowc / n1;
 
-    gptr<const nv2<R>> pin = cview<R>(S->buf[STAGE == 0 ? BUF_Y : BUF_YS]) + base;
+    // STAGE 0..3: classical RK4 stages; 4..9: Dormand-Prince stages 0..5
+    constexpr bool DP = STAGE >= 4;
+    constexpr int DS = DP ? STAGE - 4 : 0;
+    constexpr bool FIRST = STAGE == 0 || STAGE == 4, LAST = STAGE == 3 || STAGE == 9;
+    gptr<const nv2<R>> pin = cview<R>(S->buf[FIRST ? BUF_Y : BUF_YS]) + base;
     C v[1][E];
     C yq[E], yx[E], yz[E];
     if constexpr (VC::SITE) {
@@ -584,7 +591,7 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
         for (int m = 0; m < E; ++m) yq[m] = gload_nt<C>(pin, q * ns + t + T * m);
     }
     // per-line constants of the stage time (read after the barriers below)
-    constexpr double cst = STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5);
+    constexpr double cst = DP ? dp5_c(DS) : (STAGE == 0 ? 0.0 : (STAGE == 3 ? 1.0 : 0.5));
     const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
     const int nterm = S->nterm;
     if (q == 0) {
@@ -632,7 +639,16 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
     const R ky = (R)S->kap[1], kz = (R)S->kap[2];   // zero on non-trivial axes
     const bool has_g = S->dim >= 2;
     const long long mask = S->mask;
-    const R myz = (STAGE == 3 && mask >= 0) ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
+    const R myz = (LAST && mask >= 0) ? rtab[mask + n0 + yy] * rtab[mask + n0 + n1 + zz] : (R)1;
+    // Dormand-Prince: slope k_j of the stage input's sum, at offset off of the line
+    auto dp5_prev = [&](C acc, long long off) {
+#pragma unroll
+        for (int j = 0; j < DS; ++j)
+            if (dp5_a(DS + 1, j) != 0.0)
+                acc = cadd(acc, cscale(gload_nt<C>(cview<R>(S->buf[dp5_kbuf(j)]) + base, off), (R)(-a.dt * dp5_a(DS + 1, j))));
+        return acc;
+    };
+    const R hk = (R)(-a.dt * dp5_a(DS + 1, DS));   // h a_{s+1,s} for the stage's own slope
     // field A_mu at point idx of this line
     auto field = [&](int idx, R (&A)[4]) {
         A[0] = A[1] = A[2] = A[3] = (R)0;
@@ -658,6 +674,7 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
         gptr<const nv2<R>> pg = cview<R>(S->buf[BUF_T]) + base;
         gptr<const nv2<R>> pop = cview<R>(S->buf[STAGE == 3 ? BUF_ACC : BUF_Y]) + base;
         gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base;
+        gptr<nv2<R>> wk = wview<R>(S->buf[dp5_kbuf(DS < 5 ? DS : 0)]) + base;
         gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base;
         gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base;
 #pragma unroll
@@ -670,7 +687,7 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
                 for (int c = 0; c < 4; ++c) {
                     y[c] = gload_nt<C>(pin, c * ns + idx);
                     g[c] = has_g ? gload_nt<C>(pg, c * ns + idx) : cmake<C>((R)0, (R)0);
-                    y0[c] = STAGE == 0 ? cmake<C>((R)0, (R)0) : gload_nt<C>(pop, c * ns + idx);
+                    y0[c] = FIRST ? cmake<C>((R)0, (R)0) : gload_nt<C>(pop, c * ns + idx);
                 }
                 R A[4];
                 field(idx, A);
@@ -679,7 +696,7 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
 #pragma unroll
                 for (int c = 0; c < 4; ++c) sv[c] = cadd(y[c], cmul(wc[c], ph));
                 apply_pot(sv, vs, A[0], A[1], A[2], A[3]);
-                const R mk = (STAGE == 3 && mask >= 0) ? rtab[mask + idx] * myz : (R)1;
+                const R mk = (LAST && mask >= 0) ? rtab[mask + idx] * myz : (R)1;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const R bc = c < 2 ? (R)1 : (R)-1;
@@ -694,7 +711,18 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const C k = u[c];
-                    if constexpr (STAGE == 0) {
+                    if constexpr (DP) {
+                        // Dormand-Prince: y_{s+1} = y + h sum_{j<=s} a_{s+1,j} k_j (row 6: the step)
+                        const C yn = cadd(dp5_prev(DS == 0 ? y[c] : y0[c], c * ns + idx), cscale(k, hk));
+                        if (act) {
+                            if constexpr (DS < 5) {
+                                gstore_nt<C>(wk, c * ns + idx, k);
+                                gstore_nt<C>(wys, c * ns + idx, yn);
+                            } else {
+                                gstore_nt<C>(wy, c * ns + idx, cscale(yn, mk));
+                            }
+                        }
+                    } else if constexpr (STAGE == 0) {
                         if (act) gstore_nt<C>(wys, c * ns + idx, cadd(y[c], cscale(k, h2)));             // y_2
                     } else if constexpr (STAGE == 1) {
                         const C y3 = cadd(y0[c], cscale(k, h2));                                          // y_3
@@ -720,12 +748,13 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
         gptr<nv2<R>> wys = wview<R>(S->buf[BUF_YS]) + base + q * ns + t;
         gptr<nv2<R>> wacc = wview<R>(S->buf[BUF_ACC]) + base + q * ns + t;
         gptr<nv2<R>> wy = wview<R>(S->buf[BUF_Y]) + base + q * ns + t;
+        gptr<nv2<R>> wk = wview<R>(S->buf[dp5_kbuf(DS < 5 ? DS : 0)]) + base + q * ns + t;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int idx = t + T * m;
             const C g = has_g ? gload_nt<C>(pg, T * m) : cmake<C>((R)0, (R)0);
             C y0 = cmake<C>((R)0, (R)0);
-            if constexpr (STAGE == 1 || STAGE == 2) y0 = gload_nt<C>(py, T * m);
+            if constexpr (STAGE == 1 || STAGE == 2 || (DP && DS > 0)) y0 = gload_nt<C>(py, T * m);
             if constexpr (STAGE == 3) y0 = gload_nt<C>(pacc, T * m);
             R A[4];
             field(idx, A);
@@ -740,7 +769,18 @@ __attribute__((amdgpu_waves_per_eu(RdVar<R, N, V>::WAVES, 8))) row_d_kernel(Pass
             u = cadd(u, cscale(alpha3_phase(q, sz), A[3]));
             const C k = cmul_mi(u);
             // classical RK4 with the accumulator written once (as above)
-            if constexpr (STAGE == 0) {
+            if constexpr (DP) {
+                const C yn = cadd(dp5_prev(DS == 0 ? yq[m] : y0, q * ns + idx), cscale(k, hk));
+                if (act) {
+                    if constexpr (DS < 5) {
+                        gstore_nt<C>(wk, T * m, k);
+                        gstore_nt<C>(wys, T * m, yn);
+                    } else {
+                        const R mk = mask >= 0 ? rtab[mask + idx] * myz : (R)1;
+                        gstore_nt<C>(wy, T * m, cscale(yn, mk));
+                    }
+                }
+            } else if constexpr (STAGE == 0) {
                 if (act) gstore_nt<C>(wys, T * m, cadd(yq[m], cscale(k, h2)));                    // y_2
             } else if constexpr (STAGE == 1) {
                 const C y3 = cadd(y0, cscale(k, h2));                                              // y_3
@@ -956,7 +996,7 @@ __global__ void __launch_bounds__((LineVar<R, N, WIDE>::T)) line_kernel(PassArgs
 }
 
 // Kernel table of one (precision, N) instantiation.
-struct RowVariant { const void* stage[4]; int threads, rows; size_t lds; };
+struct RowVariant { const void* stage[4]; const void* dp5[6]; int threads, rows; size_t lds; };   // RK4 / Dormand-Prince stages
 struct CdVariant { const void* fn[2][2]; int threads, w; size_t lds; };   // [axis - 1][accumulate]
 struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
@@ -978,6 +1018,9 @@ RowVariant make_row_variant() {
     using VC = RdVar<R, N, V>;
     return RowVariant{{(const void*)row_d_kernel<R, N, V, 0>, (const void*)row_d_kernel<R, N, V, 1>,
                        (const void*)row_d_kernel<R, N, V, 2>, (const void*)row_d_kernel<R, N, V, 3>},
+                      {(const void*)row_d_kernel<R, N, V, 4>, (const void*)row_d_kernel<R, N, V, 5>,
+                       (const void*)row_d_kernel<R, N, V, 6>, (const void*)row_d_kernel<R, N, V, 7>,
+                       (const void*)row_d_kernel<R, N, V, 8>, (const void*)row_d_kernel<R, N, V, 9>},
                       VC::THREADS, VC::ROWS, VC::BYTES};
 }
 template <class R, int N, int V>

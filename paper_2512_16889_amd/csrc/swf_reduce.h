@@ -71,6 +71,9 @@ struct BwArgs {
     const int* step;
     double t_out, dt;
     int stage;
+    double cst;          // the stage's time node: t = t_out - (step + cst) dt
+    int nst;             // stages per step (4 RK4, 6 Dormand-Prince)
+    double wst[6];       // the stages' quadrature weights (sum 1)
     int nvert;
     double2* part;       // [vertex][stage][block][3]
     double2* M;          // [vertex][3] accumulated integrals (device, double)

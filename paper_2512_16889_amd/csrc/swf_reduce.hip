@@ -337,15 +337,14 @@ __global__ void __launch_bounds__(RED_THREADS) bw_stage_kernel(BwArgs a) {
         double2 s = shw[0][3 * p + c];
 #pragma unroll
         for (int w = 1; w < NW; ++w) s = dadd(s, shw[w][3 * p + c]);
-        const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
-        const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+        const double ts = a.t_out - (double)(*a.step) * a.dt - a.cst * a.dt;
         // phase of the term: -(k0 + [E_V]) t for (s,s) / (s,b), (E_U - k0) t for (b,s)
         double w = -a.verts[G->vtx[0]].k0;
         if (c == 1) w += a.solves[G->su[G->ui[j]]].E;
         if (c == 2) w -= a.solves[G->sv[G->vi[j]]].E;
         double sn, cs;
         sincos(w * ts, &sn, &cs);
-        a.part[(((long long)G->vtx[j] * 4 + a.stage) * gridDim.x + blockIdx.x) * 3 + c] = dmul(d2(cs, sn), s);
+        a.part[(((long long)G->vtx[j] * a.nst + a.stage) * gridDim.x + blockIdx.x) * 3 + c] = dmul(d2(cs, sn), s);
     }
 }
 
@@ -370,8 +369,7 @@ __global__ void __launch_bounds__(RED_THREADS) bw_packet_stage_kernel(BwArgs a) 
     const SolveDev* SU = a.solves + V->su;
     const SolveDev* SV = a.solves + V->sv;
     const int role = a.stage == 0 ? BUF_Y : BUF_YS;
-    const double cst = (a.stage == 0) ? 0.0 : (a.stage == 3 ? 1.0 : 0.5);
-    const double ts = a.t_out - (double)(*a.step) * a.dt - cst * a.dt;
+    const double ts = a.t_out - (double)(*a.step) * a.dt - a.cst * a.dt;
     const C* ctab = reinterpret_cast<const C*>(a.ctab);
     const int nm = V->nmodes;
     // c_m e^{-i k0_m t} eps_m of every mode and its phase tables
@@ -432,7 +430,7 @@ __global__ void __launch_bounds__(RED_THREADS) bw_packet_stage_kernel(BwArgs a) 
         }
     }
     // partials layout [vertex][stage][block][3]
-    double2* out = a.part + ((long long)a.packets[blockIdx.y] * 4 + a.stage) * (long long)gridDim.x * 3;
+    double2* out = a.part + ((long long)a.packets[blockIdx.y] * a.nst + a.stage) * (long long)gridDim.x * 3;
     block_sum_store<3>(acc, out);
 }
 
@@ -441,15 +439,14 @@ __global__ void bw_accum_kernel(BwArgs a, int nblk) {
     if (gid >= a.nvert * 3) return;
     const int v = gid / 3, term = gid % 3;
     const SolveDev* SU = a.solves + a.verts[v].su;
-    const double wst[4] = {1.0, 2.0, 2.0, 1.0};
     double2 s = d2(0, 0);
-    for (int st = 0; st < 4; ++st) {
-        const double2* p = a.part + ((long long)v * 4 + st) * (long long)nblk * 3;
+    for (int st = 0; st < a.nst; ++st) {
+        const double2* p = a.part + ((long long)v * a.nst + st) * (long long)nblk * 3;
         double2 ss = d2(0, 0);
         for (int b = 0; b < nblk; ++b) ss = dadd(ss, p[(long long)b * 3 + term]);
-        s = dadd(s, dsc(ss, wst[st]));
+        s = dadd(s, dsc(ss, a.wst[st]));
     }
-    const double f = -a.dt / 6.0 * SU->dV;
+    const double f = -a.dt * SU->dV;
     double2* M = a.M + (long long)v * 3 + term;
     *M = dadd(*M, dsc(s, f));
 }

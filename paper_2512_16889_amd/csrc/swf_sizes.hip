@@ -27,12 +27,14 @@ SWF_DEFINE(16)
 SWF_DEFINE(32)
 SWF_DEFINE(64)
 SWF_DEFINE(128)
+#elif SWF_GROUP == 7
 SWF_DEFINE(48)
 SWF_DEFINE(96)
+SWF_DEFINE(192)
+#elif SWF_GROUP == 8
 SWF_DEFINE(40)
 SWF_DEFINE(80)
 SWF_DEFINE(160)
-SWF_DEFINE(192)
 #elif SWF_GROUP == 1
 SWF_DEFINE(256)
 #elif SWF_GROUP == 2

@@ -29,6 +29,8 @@ _lib = C.CDLL(LIB_PATH)
 
 SWF_OK, SWF_E_ARG, SWF_E_NOMEM, SWF_E_HIP, SWF_E_ORDER, SWF_E_UNSUPPORTED, SWF_E_NONFINITE = range(7)
 SWF_FP64, SWF_MIXED = 0, 1
+SWF_RK4, SWF_DP5 = 0, 1
+STEPPERS = {"rk4": SWF_RK4, "dp5": SWF_DP5}
 AMP_PAIR1, AMP_PAIR2, AMP_BW, AMP_BW_PARTIAL = 0, 1, 2, 3
 P_MARGINAL_E, P_MARGINAL_POS, P_PAIR, P_BW = 0, 1, 2, 3
 STAT_ROW, STAT_COLY, STAT_COLZ, STAT_BW, STAT_OTHER = range(5)
@@ -66,7 +68,7 @@ class Options(C.Structure):
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int), ("batched", C.c_int),
                 ("profile", C.c_int), ("tune", C.c_int), ("tune_cache", C.c_char_p), ("chunk", C.c_int),
                 ("force_variant", C.c_int), ("persistent", C.c_int), ("bw_partial", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("stepper", C.c_int)]
 
 
 _P = C.POINTER
@@ -187,6 +189,7 @@ def workspace_size(problem, precision: str = "fp64", bw_partial: bool = False) -
     opt.prec = SWF_FP64 if precision == "fp64" else SWF_MIXED
     opt.batched = 1
     opt.bw_partial = int(bw_partial)
+    opt.stepper = STEPPERS[getattr(problem.window, "scheme", "rk4")]
     nbytes = C.c_size_t(0)
     code = _lib.swf_workspace_size(grids, len(problem.grids), terms, ffirst, len(problem.fields), solves,
                                    len(problem.solves), verts, len(problem.vertices), C.byref(win), C.byref(opt),
@@ -219,6 +222,7 @@ class Context:
         self.opt.persistent = int(persistent)
         self.opt.bw_partial = int(bw_partial)
         self.opt.check_every = int(check_every)
+        self.opt.stepper = STEPPERS[getattr(problem.window, "scheme", "rk4")]
         self._tune_cache = tune_cache.encode() if tune_cache else None
         self.opt.tune_cache = self._tune_cache
         self.opt.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)

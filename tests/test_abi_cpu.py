@@ -122,3 +122,26 @@ def test_in_state_validation(S):
     assert code == S.SWF_E_UNSUPPORTED and "in- and out-states" in msg
     prob.solves[1].kind = 4
     assert wsize(S, prob)[0] == S.SWF_E_ARG
+
+
+def test_stepper_validation(S):
+    import dataclasses
+    prob = W.config_bw_1d(n=64, L=100.0, steps=4)
+    w = prob.window
+    prob = dataclasses.replace(prob, window=W.Window(w.t_in, w.t_out, w.dt, "dp5"))
+    grids, terms, ffirst, solves, verts, win = S.marshal(prob)
+
+    def size(**kw):
+        opt = S.Options()
+        for k, v in kw.items():
+            setattr(opt, k, v)
+        out = C.c_size_t(0)
+        code = S._lib.swf_workspace_size(grids, 1, terms, ffirst, 1, solves, 2, verts, 1, C.byref(win), C.byref(opt),
+                                         C.byref(out))
+        return code, out.value
+    c4, b4 = size(stepper=S.SWF_RK4)
+    c5, b5 = size(stepper=S.SWF_DP5)
+    assert c4 == 0 and c5 == 0 and b5 > b4            # eight state arrays per solve instead of four
+    assert size(stepper=S.SWF_DP5, bw_partial=1)[0] == S.SWF_E_UNSUPPORTED
+    assert size(stepper=7)[0] == S.SWF_E_ARG
+    assert S.workspace_size(prob) == b5               # the binding takes the stepper from the window
