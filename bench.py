@@ -76,6 +76,13 @@ def workload(name):
     if name == "1d":
         return W.config_1d(), ("(1+1)D Schwinger: A_1 = 1.5 sech^2(0.2 t) sech^2(0.1 x), n=1024 over [-100,100), "
                                "dt=0.02, 6000-step window, one solve")
+    if name == "2d-small":
+        import dataclasses
+        p = W.config_2d()
+        g = dataclasses.replace(p.grids[0], n=[128, 128, 1])
+        return dataclasses.replace(p, grids=[g], solves=p.solves[:8]), (
+            "(2+1)D Schwinger field of the 2D workload on a 128^2 lattice over [-80,80)^2, 8 of its solves, "
+            "dt=0.02 (launch-bound: microsecond passes)")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -143,7 +150,8 @@ def observables(ctx, prob):
 
 
 def run_path(S, torch, prob, precision, K, Wm, batched=True, tune=True, variant=None, chunk=0, graph=False,
-             bw_partial=False, max_solves=0, label="", reset_after_warmup=False, tune_cache=None):
+             bw_partial=False, max_solves=0, label="", reset_after_warmup=False, tune_cache=None, graph_steps=0,
+             profile=None):
     """Time K RK4 steps (after Wm untimed ones) of every solve of prob.
     With reset_after_warmup the context is returned to t_out after the Wm
     steps, so the K timed steps can span the whole window.
@@ -160,8 +168,10 @@ def run_path(S, torch, prob, precision, K, Wm, batched=True, tune=True, variant=
         sub = sub_problem(prob, b)
         print(f"[bench] {label}: context of {len(b)} solves, {len(sub.vertices)} vertices, "
               f"{S.workspace_size(sub, precision, bw_partial) / 1e9:.1f} GB", file=sys.stderr, flush=True)
-        ctx = S.Context(sub, precision=precision, batched=batched, use_graph=graph, profile=not graph, tune=tune,
-                        chunk=chunk, variant=variant, bw_partial=bw_partial, tune_cache=tune_cache)
+        prof = (not graph) if profile is None else profile
+        ctx = S.Context(sub, precision=precision, batched=batched, use_graph=graph, profile=prof, tune=tune,
+                        chunk=chunk, variant=variant, bw_partial=bw_partial, tune_cache=tune_cache,
+                        graph_steps=graph_steps)
         reports.append(ctx.tune_report())
         if Wm:
             ctx.step(Wm)
@@ -175,7 +185,7 @@ def run_path(S, torch, prob, precision, K, Wm, batched=True, tune=True, variant=
         ctx.sync()
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-        if not graph:
+        if prof:
             for k in range(6):
                 n, ms, by = ctx.kernel_stats(k)
                 stats[k][0] += n
@@ -511,14 +521,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed RK4 steps of the whole batch")
     ap.add_argument("--warmup", type=int, default=5, help="untimed RK4 steps before the timed ones")
-    ap.add_argument("--workload", default="bw3d", choices=["bw3d", "2d", "3d", "ragged", "1d"])
+    ap.add_argument("--workload", default="bw3d", choices=["bw3d", "2d", "3d", "ragged", "1d", "2d-small"])
     ap.add_argument("--full-window", action="store_true",
                     help="time the workload's whole window (--steps is ignored; the warmup steps run first "
                          "and the context is reset)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain per-instance path")
-    ap.add_argument("--graph", action="store_true", help="also time the hipGraph replay of the FP64 batched path")
+    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay leg of the FP64 batched path")
+    ap.add_argument("--graph-steps", type=int, default=16, help="time steps captured per graph of the replay leg")
+    ap.add_argument("--graph-compare", action="store_true",
+                    help="only compare eager launches (no event timing), one-step and multi-step graph replay")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16, help="CPU baseline processes (capped by the cores)")
     ap.add_argument("--cpu-n", type=int, default=80, help="3D lattice points per axis of the CPU sample")
@@ -592,6 +605,16 @@ def main():
     if args.pair_matrix:
         print(json.dumps(pair_matrix_bench(S, torch, args.pair_matrix)), flush=True)
         return
+    if args.graph_compare:
+        res = {}
+        for name, kw in (("eager", {}), ("graph, 1 step", {"graph": True}),
+                         (f"graph, {args.graph_steps} steps", {"graph": True, "graph_steps": args.graph_steps})):
+            wall, *_ = run_path(S, torch, prob, "fp64", K, Wm, tune_cache=args.tune_cache, profile=False, label=name,
+                                **kw)
+            res[name] = {"ms_per_step": wall / K * 1e3}
+            print(f"[bench] {name}: {wall / K * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+        print(json.dumps({"workload": desc, "steps": K, "warmup": Wm, "paths": res}), flush=True)
+        return
     if args.matched_error:
         if args.workload not in ("1d", "2d", "3d"):
             raise SystemExit("--matched-error takes the 1d, 2d or 3d workload")
@@ -619,8 +642,9 @@ def main():
     paths, obs = {}, {}
     if not args.no_fp64:
         paths["fp64_batched"], obs["fp64"] = leg("fp64 batched", "fp64")
-        if args.graph:
-            paths["fp64_batched_graph"], _ = leg("fp64 batched, graph replay", "fp64", graph=True)
+        if not args.no_graph:
+            paths["fp64_batched_graph"], _ = leg(f"fp64 batched, graph replay ({args.graph_steps} steps per graph)",
+                                                 "fp64", graph=True, graph_steps=args.graph_steps)
         if not args.no_plain:
             paths["fp64_plain"], _ = leg("fp64 plain per-instance", "fp64", batched=False, tune=False, variant=None)
     if not args.no_mixed:

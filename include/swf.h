@@ -159,6 +159,11 @@ typedef struct {
                                control).  BW integrals take the tableau's weights over
                                the stages.  SWF_DP5 does not combine with bw_partial or
                                the persistent 1D kernel (the pass path runs instead)    */
+    int graph_steps;        /* with use_graph: > 1 also captures that many consecutive
+                               time steps as one graph, replayed while at least that
+                               many steps remain (the one-step graph takes the rest,
+                               and every step when check_every > 0); 0 or 1: one step
+                               per graph                                                */
 } swf_options;
 
 typedef enum { SWF_RK4 = 0, SWF_DP5 = 1 } swf_stepper;

@@ -621,6 +621,7 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     // ---- groups and work items
     if (opt->chunk < 0) FAIL(SWF_E_ARG, "chunk must be >= 0");
     if (opt->check_every < 0) FAIL(SWF_E_ARG, "check_every must be >= 0");
+    if (opt->graph_steps < 0) FAIL(SWF_E_ARG, "graph_steps must be >= 0");
     for (int g = 0; g < n_grids; ++g) {
         std::vector<int> all;
         for (int i = 0; i < n_solves; ++i) if (P.solves[i].grid == g) all.push_back(i);
@@ -711,8 +712,9 @@ struct swf_ctx {
     std::vector<char> kvalid;
     std::vector<int> bw_done;
     std::vector<cd> bw_cache;     // 3 terms finite + 3 past per vertex
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graph_k = nullptr;   // one step; graph_steps steps
+    hipGraphExec_t gexec = nullptr, gexec_k = nullptr;
+    int graph_k_steps = 0;
     std::string err;
     std::string tune_path;
     std::string tune_report;
@@ -1143,19 +1145,34 @@ static int line_steps(swf_ctx* ctx, int n) {
     return SWF_OK;
 }
 
-static int build_graph(swf_ctx* ctx) {
+// Capture `steps` consecutive time steps (every launch, the device step
+// counter advanced by each) as one graph.
+static int capture_steps(swf_ctx* ctx, int steps, hipGraph_t* graph, hipGraphExec_t* exec) {
     HIPCHK(hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal));
-    int r = enqueue_step(ctx);
+    int r = SWF_OK;
+    for (int i = 0; i < steps && !r; ++i) r = enqueue_step(ctx);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->st, &g);
-    if (r) return r;
+    if (r) {
+        if (g) hipGraphDestroy(g);
+        return r;
+    }
     if (e != hipSuccess) {
         ctx->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
         return SWF_E_HIP;
     }
-    ctx->graph = g;
-    HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    *graph = g;
+    HIPCHK(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
     return SWF_OK;
+}
+
+// The one-step graph, and with options.graph_steps > 1 a graph of that many
+// steps, replayed while at least that many steps remain.
+static int build_graph(swf_ctx* ctx) {
+    int r = capture_steps(ctx, 1, &ctx->graph, &ctx->gexec);
+    if (r || ctx->opt.graph_steps <= 1) return r;
+    ctx->graph_k_steps = std::min(ctx->opt.graph_steps, ctx->P.steps);
+    return capture_steps(ctx, ctx->graph_k_steps, &ctx->graph_k, &ctx->gexec_k);
 }
 
 // ------------------------------------------------------------ autotuner
@@ -1817,14 +1834,20 @@ swf_status swf_step(swf_ctx* ctx, int n_steps, int* steps_left) {
             if (K > 0 && (ctx->step + done) % K == 0 && (r = check(ctx->step + done))) return (swf_status)r;
         }
     } else {
-        for (int i = 0; i < n_steps; ++i) {
+        for (int i = 0; i < n_steps;) {
+            if (ctx->gexec_k && K == 0 && n_steps - i >= ctx->graph_k_steps) {
+                HIPCHK(hipGraphLaunch(ctx->gexec_k, ctx->st));
+                i += ctx->graph_k_steps;
+                continue;
+            }
+            ++i;
             if (ctx->gexec) {
                 HIPCHK(hipGraphLaunch(ctx->gexec, ctx->st));
             } else {
                 r = enqueue_step(ctx);
                 if (r) return (swf_status)r;
             }
-            if (K > 0 && (ctx->step + i + 1) % K == 0 && (r = check(ctx->step + i + 1))) return (swf_status)r;
+            if (K > 0 && (ctx->step + i) % K == 0 && (r = check(ctx->step + i))) return (swf_status)r;
         }
     }
     if (n_steps > 0) {
@@ -2211,6 +2234,8 @@ void swf_free(swf_ctx* ctx) {
     for (auto e : ctx->ev_free) hipEventDestroy(e);
     if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) hipGraphDestroy(ctx->graph);
+    if (ctx->gexec_k) hipGraphExecDestroy(ctx->gexec_k);
+    if (ctx->graph_k) hipGraphDestroy(ctx->graph_k);
     if (ctx->own_arena && ctx->arena) hipFree(ctx->arena);
     if (ctx->pm_buf) hipFree(ctx->pm_buf);
     if (ctx->ev_in) hipEventDestroy(ctx->ev_in);

@@ -68,7 +68,7 @@ class Options(C.Structure):
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int), ("batched", C.c_int),
                 ("profile", C.c_int), ("tune", C.c_int), ("tune_cache", C.c_char_p), ("chunk", C.c_int),
                 ("force_variant", C.c_int), ("persistent", C.c_int), ("bw_partial", C.c_int),
-                ("check_every", C.c_int), ("stepper", C.c_int)]
+                ("check_every", C.c_int), ("stepper", C.c_int), ("graph_steps", C.c_int)]
 
 
 _P = C.POINTER
@@ -205,7 +205,7 @@ class Context:
     def __init__(self, problem, precision: str = "fp64", use_graph: bool = False, batched: bool = True,
                  profile: bool = False, device_workspace: bool = True, tune: bool = False,
                  tune_cache: str | None = None, chunk: int = 0, variant: int | None = None,
-                 persistent: bool = True, bw_partial: bool = False, check_every: int = 0):
+                 persistent: bool = True, bw_partial: bool = False, check_every: int = 0, graph_steps: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the SWF solver runs on the GPU only; no device is visible")
         self.problem = problem
@@ -222,6 +222,7 @@ class Context:
         self.opt.persistent = int(persistent)
         self.opt.bw_partial = int(bw_partial)
         self.opt.check_every = int(check_every)
+        self.opt.graph_steps = int(graph_steps)
         self.opt.stepper = STEPPERS[getattr(problem.window, "scheme", "rk4")]
         self._tune_cache = tune_cache.encode() if tune_cache else None
         self.opt.tune_cache = self._tune_cache

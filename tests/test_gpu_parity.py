@@ -190,6 +190,30 @@ def test_graph_replay_bitwise_equals_eager(S):
             assert g.marginal(i) == e.marginal(i)
 
 
+@pytest.mark.parametrize("graph_steps", [5, 16])
+def test_multi_step_graph_bitwise_equals_eager(S, graph_steps):
+    # graph_steps consecutive steps per graph, the one-step graph for the rest;
+    # a BW problem so the vertex integrals ride along, and a run with the
+    # in-loop check (every step then replays the one-step graph)
+    P = 2 * np.pi * 4 / 160.0
+    prob = W.config_bw_1d(P=P, n=128, L=160.0, dt=0.1, t_half=5.0)
+    with S.Context(prob, precision="fp64", use_graph=True, graph_steps=graph_steps) as g, \
+            S.Context(prob, precision="fp64") as e:
+        for chunk in (7, 23, 1, 69):
+            g.step(chunk)
+            e.step(chunk)
+            for i in range(len(prob.solves)):
+                assert np.array_equal(g.get_psi(i), e.get_psi(i))
+        assert g.steps() == e.steps()
+        want = e.bw(0)
+        assert g.bw(0) == want
+    with S.Context(prob, precision="fp64", use_graph=True, graph_steps=graph_steps, check_every=3) as c:
+        c.step()
+        assert c.bw(0) == want
+        for i in range(2):
+            assert relerr(c.get_psi(i), SWFSolve(prob, i).run()) < 1e-10
+
+
 def test_repeatable_bitwise(S):
     prob = problem(3, (16, 16, 16), (18.0, 18.0, 18.0), kinds=(0,), spins=(1,), t_half=1.0)
     res = []
