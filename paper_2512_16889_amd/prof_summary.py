@@ -1,7 +1,9 @@
 """Summaries of rocprofv3 output for the solver's kernels.
 
 ``python -m paper_2512_16889_amd.prof_summary stats <kernel_stats.csv>``
-prints a markdown table of the per-kernel dispatch statistics.
+prints a markdown table of the per-kernel dispatch statistics;
+``... launches <kernel_trace.csv> [top]`` the same from the trace, per kernel
+and launch grid.
 
 ``python -m paper_2512_16889_amd.prof_summary traffic <pmc_fetch.csv>
 <pmc_write.csv> <copy_fetch.csv> <copy_write.csv> <copy_bytes>`` prints, as
@@ -31,6 +33,25 @@ def stats_table(path, top=16):
     for r in rows[:top]:
         out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def launch_table(path, top=24, min_us=0.0):
+    """Markdown table of a kernel trace grouped by kernel and launch grid, so
+    that batched and per-solve launches of one kernel are told apart."""
+    groups = {}
+    for r in _rows(path):
+        key = (r["Kernel_Name"], int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in groups.values())
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    out = ["| kernel | grid | calls | avg us | min us | max us | % of time |", "|---|---|---|---|---|---|---|"]
+    for (name, gx, gy), d in rows[:top]:
+        avg = statistics.mean(d)
+        if avg < min_us:
+            continue
+        out.append(f"| `{name[:80]}` | {gx} x {gy} | {len(d)} | {avg:.1f} | {min(d):.1f} | {max(d):.1f} | "
+                   f"{100.0 * sum(d) / total:.2f} |")
     return "\n".join(out)
 
 
@@ -68,5 +89,7 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats_table(sys.argv[2]))
+    elif sys.argv[1] == "launches":
+        print(launch_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 24))
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:6], float(sys.argv[6])), indent=1))
