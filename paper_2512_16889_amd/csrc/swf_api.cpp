@@ -1433,10 +1433,15 @@ static int pair_gemm(swf_ctx* ctx, const std::vector<int>& ra, int asrc, int aro
     a.splits = (int)((ns + a.per - 1) / a.per);
     a.ns = ns;
     a.dim = G.dim;
+    a.n0 = G.n[0];
+    a.n1 = G.n[1];
+    a.n2 = G.n[2];
     for (int j = 0; j < 3; ++j) {
         a.x0[j] = j < G.dim ? -0.5 * G.L[j] : 0.0;
         a.dx[j] = j < G.dim ? G.L[j] / G.n[j] : 0.0;
+        a.dk[j] = ctx->P.hs[s0].dk[j];
     }
+    a.ctab = ctx->d_ctab();
     a.proj = proj;
     // scratch: row descriptors, then the partial tiles and their sum
     const size_t part_bytes = tile_bytes * (size_t)(a.splits + 1);

@@ -102,7 +102,10 @@ struct PairArgs {
     int proj;            // 0, or +1 / -1: Pi_+ / Pi_- of k-space states on both sides
     long long ns;        // sites of the (common) lattice
     int dim;
+    int n0, n1, n2;      // lattice points per axis (1 on trivial axes)
     double x0[3], dx[3]; // lattice coordinates x_i = x0 + i dx
+    double dk[3];        // lattice wavenumber steps 2 pi / L_j
+    const void* ctab;    // complex tables (the solves' background phase tables)
     int tiles_m, tiles_n, splits;
     long long per;       // sites per split (a multiple of the staging chunk)
     int mp, np;          // padded output dimensions (multiples of the 64-row tile)
