@@ -706,6 +706,7 @@ struct swf_ctx {
     bool own_arena = false;
     int step = 0;
     size_t lds_max = 65536;       // dynamic LDS one workgroup may use on this device
+    int ncu = 256;                // compute units of this device
     void* pm_buf = nullptr;       // pair-matrix scratch (grown on demand, freed by swf_free)
     size_t pm_bytes = 0;
     void* noalloc_scratch = nullptr;   // this device's static scratch array (swf_pair_matrix_noalloc)
@@ -820,12 +821,14 @@ static double group_sites(swf_ctx* ctx, const Group& g) {
 }
 
 // Launch one pass kernel over n items starting at item offset `it`.
+// maxblocks > 0: a persistent kernel that loops over the items with the grid's
+// stride, given at most that many workgroups per blockIdx.y.
 static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threads, size_t lds, swf::PassArgs a,
-                  int kind, double bytes, int gy = 1) {
+                  int kind, double bytes, int gy = 1, int maxblocks = 0) {
     if (nitems <= 0) return SWF_OK;
     a.items = ctx->d_items() + it;
     a.nitems = nitems;
-    const int blocks = nitems;
+    const int blocks = maxblocks > 0 ? std::min(nitems, maxblocks) : nitems;
     void* args[] = {&a};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = ctx->opt.profile && !ctx->gexec;
@@ -896,8 +899,9 @@ static int cd_pass(swf_ctx* ctx, const Group& g, int axis, int src, int kind) {
     a.dst = swf::BUF_T;
     const int n = axis == 1 ? g.n_coly[v] : g.n_colz[v];
     const size_t it = axis == 1 ? g.it_coly[v] : g.it_colz[v];
+    // persistent y passes: one workgroup per compute unit (all the LDS they leave room for)
     return launch(ctx, cv.fn[axis - 1][accum], n, it, cv.threads, cv.lds, a, kind,
-                  (2.0 + accum) * 4.0 * ctx->P.csize * group_sites(ctx, g), 4);
+                  (2.0 + accum) * 4.0 * ctx->P.csize * group_sites(ctx, g), 4, cv.pipe && !accum ? ctx->ncu : 0);
 }
 
 // The passes of one RK4 stage of a group: the column derivatives of the stage
@@ -1754,6 +1758,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
         INITCHK(hipGetDevice(&dev));
         INITCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         ctx->lds_max = (size_t)lds;
+        INITCHK(hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, dev));
         // this device's copy of the static scratch (swf_pair_matrix_noalloc)
         INITCHK(scratch_address(dev, &ctx->noalloc_scratch));
     }

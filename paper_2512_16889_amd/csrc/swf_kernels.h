@@ -431,6 +431,14 @@ template <class R, int N, int V> struct CdVar {
     static constexpr int W = imax(1, imin(imin(WANT * (V >= 2 ? 2 : 1), 1024 / T), WMAX));
     static constexpr int THREADS = T * W;
     static constexpr size_t BYTES = (size_t)N * W * sizeof(cpx<R>);
+    // A tile whose exchange buffer and twiddles leave room for only one
+    // workgroup per compute unit (160 KB of LDS) would leave HBM idle while it
+    // transforms; those y passes run as a persistent loop over the tiles that
+    // loads the next tile while this one is transformed.  Only where the
+    // workgroup has at most 512 threads (with more, the prefetch would spill)
+    // and the tile is at most 8 columns wide: every lattice length is a
+    // multiple of 8, so such tiles are never partial.
+    static constexpr bool PIPE = 2 * (BYTES + N * sizeof(cpx<R>)) > 163840 && THREADS <= 512 && 8 % W == 0;
     static_assert(plan_ok<N, T, PL>(), "column derivative variant violates the FFT plan constraints");
 };
 
@@ -452,48 +460,98 @@ __global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassAr
     const int t = tid / W;
     const int q = blockIdx.y;                       // output component
     const int src = AXIS == 1 ? 3 - q : (q ^ 2);    // the component alpha^j takes
-    // one tile = W adjacent columns of one solve at one fixed other-axis index
-    const int2 it = a.items[blockIdx.x];
-    const SolveDev* __restrict__ S = a.solves + it.x;
-    const int n0 = S->n[0], n1 = S->n[1];
+    // (the persistent loop only for the y pass: the z pass's partial sums would
+    // double the registers a prefetch holds)
+    constexpr bool PIPE = VC::PIPE && !ACCUM;
+    // Every solve of a launch has the same lengths (so the same twiddles); a
+    // tile's own descriptor words (its item and its solve's arrays) are read
+    // through the constant address space, as scalar loads, which do not wait
+    // for the previous tile's stores still in flight.
+    const SolveDev* S0 = a.solves + a.items[blockIdx.x].x;
+    const int n0 = S0->n[0], n1 = S0->n[1];
     const int ntx = (n0 + W - 1) / W;
-    const int other = it.y / ntx;
-    const int x = (it.y % ntx) * W + xl;
-    const bool act = x < n0;
+    const long long ns = S0->nsites;
     const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
-    const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
-    const long long base = obase + (act ? x : 0) + (long long)t * stride;
-    const long long ns = S->nsites;
+    const double kscale = S0->dk[AXIS] / (double)N;
     gptr<const nv2<R>> ctab = cview<R>(a.ctab);
-    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[AXIS] + i);
-
-    C v[1][E];
-    C g[E];
-    {
-        gptr<const nv2<R>> p = cview<R>(S->buf[a.src]) + base + src * ns;
+    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S0->tw[AXIS] + i);
+    using cword = const unsigned long long __attribute__((address_space(4)))*;
+    struct Tile {
+        unsigned long long src, dst;   // the solve's stage input and G arrays
+        long long base;
+        bool act;
+    };
+    auto tile = [&](int item) {
+        const unsigned long long w = *(cword)(a.items + item);
+        const int solve = (int)(unsigned)w, ty = (int)(w >> 32);
+        const int other = ty / ntx;
+        const int x = (ty % ntx) * W + xl;
+        Tile u;
+        // (no partial persistent tiles: their stores need no branch)
+        u.act = PIPE || x < n0;
+        const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
+        u.base = obase + (u.act ? x : 0) + (long long)t * stride;
+        const SolveDev* S = a.solves + solve;
+        u.src = *(cword)(&S->buf[a.src]);
+        u.dst = *(cword)(&S->buf[a.dst]);
+        return u;
+    };
+    auto load = [&](const Tile& u, C (&v)[E], C (&g)[E]) {
+        gptr<const nv2<R>> p = cview<R>((const void*)u.src) + u.base + src * ns;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[0][m] = gload_nt<C>(p, (long long)(T * m) * stride);
+        for (int m = 0; m < E; ++m) v[m] = gload_nt<C>(p, (long long)(T * m) * stride);
         if constexpr (ACCUM) {
             // the partial sum of the earlier axis, loaded ahead of the transforms
-            gptr<const nv2<R>> pg = cview<R>(S->buf[a.dst]) + base + q * ns;
+            gptr<const nv2<R>> pg = cview<R>((const void*)u.dst) + u.base + q * ns;
 #pragma unroll
             for (int m = 0; m < E; ++m) g[m] = gload_nt<C>(pg, (long long)(T * m) * stride);
         }
-    }
-    fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
-    const double kscale = S->dk[AXIS] / (double)N;
+    };
+
+    // Order of a persistent iteration: issue the next tile's loads, transform
+    // this tile, store it, then take the next tile's values (waiting for its
+    // loads but not for the stores just issued).  The first tile's loads are
+    // waited for before the loop, so that at the loop's top only stores are
+    // in flight and nothing there waits for them.
+    int item = blockIdx.x;
+    Tile u = tile(item);
+    C v[1][E], g[E];
+    load(u, v[0], g);
+    if constexpr (PIPE) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const C w = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
-        v[0][m] = AXIS == 1 ? alpha2_phase(q, w) : alpha3_phase(q, w);
+        for (int m = 0; m < E; ++m) asm volatile("" ::"v"(v[0][m].x), "v"(v[0][m].y));
     }
-    fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
-    if (act) {
-        gptr<nv2<R>> p = wview<R>(S->buf[a.dst]) + base + q * ns;
+    for (;;) {
+        const int next = item + (int)gridDim.x;
+        const bool more = PIPE && next < a.nitems;
+        Tile un;
+        C vn[E], gn[E];
+        if (more) {
+            un = tile(next);
+            load(un, vn, gn);
+        }
+        fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
-            gstore_nt<C>(p, (long long)(T * m) * stride, o);
+            const C w = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
+            v[0][m] = AXIS == 1 ? alpha2_phase(q, w) : alpha3_phase(q, w);
+        }
+        fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+        if (u.act) {
+            gptr<nv2<R>> p = wview<R>((void*)u.dst) + u.base + q * ns;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
+                gstore_nt<C>(p, (long long)(T * m) * stride, o);
+            }
+        }
+        if (!more) break;
+        item = next;
+        u = un;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            v[0][m] = vn[m];
+            g[m] = gn[m];
         }
     }
 }
@@ -997,7 +1055,7 @@ __global__ void __launch_bounds__((LineVar<R, N, WIDE>::T)) line_kernel(PassArgs
 
 // Kernel table of one (precision, N) instantiation.
 struct RowVariant { const void* stage[4]; const void* dp5[6]; int threads, rows; size_t lds; };   // RK4 / Dormand-Prince stages
-struct CdVariant { const void* fn[2][2]; int threads, w; size_t lds; };   // [axis - 1][accumulate]
+struct CdVariant { const void* fn[2][2]; int threads, w; size_t lds; int pipe; };   // [axis - 1][accumulate]; pipe: persistent y pass
 struct ColVariant { const void* fn[2][3]; int threads, w; size_t lds; };
 struct SizeKernels {
     int nvar;                      // tile variants of the stepping passes
@@ -1034,6 +1092,7 @@ CdVariant make_cd_variant() {
     c.threads = VC::THREADS;
     c.w = VC::W;
     c.lds = VC::BYTES;
+    c.pipe = VC::PIPE ? 1 : 0;
     return c;
 }
 template <class R, int N, int V>

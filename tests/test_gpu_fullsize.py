@@ -3,7 +3,8 @@
 * 2D grids of every benchmark length (256 ... 1024): one RK4 step from a
   random state, element by element against the oracle's step, for each tile
   variant forced in turn (every kernel the autotuner can pick) and both
-  precisions.
+  precisions; and narrow grids of 768 and 1024 points along y with enough
+  solves that the persistent y pass steps several tiles per workgroup.
 * 3D: the lengths 256 and 320 on each axis in turn (the other axes short), so
   the row pass and both column passes of those lengths are checked against
   the oracle.
@@ -74,6 +75,18 @@ def one_step_case(S, key, prob, prec, variant, persistent=True):
 def test_2d_full_length_one_step(S, n, variant, prec):
     prob = W.config_2d(n=n, n_solves=1, seed=n)
     one_step_case(S, ("2d", n), prob, prec, variant)
+
+
+@pytest.mark.parametrize("n", [768, 1024])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_2d_persistent_column_loop(S, n, variant):
+    # FP64 y passes of 768 and 1024 points whose tiles fill the LDS run as one
+    # persistent workgroup per compute unit: 72 solves of 64 x n give 576
+    # tiles, so each workgroup steps two or three of them (the last round
+    # ragged), loading the next while it transforms the current one
+    prob = W.config_2d(n=n, n_solves=72, seed=n + 1)
+    prob.grids = [W.Grid(2, [64, n, 1], [20.0, 160.0, 1.0])]
+    one_step_case(S, ("2d_narrow", n), prob, "fp64", variant)
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
