@@ -19,7 +19,10 @@ strong-field processes in multidimensional background fields"):
                   eq. (scatDirac), discretised pseudo-spectrally in space and
                   integrated with classical RK4 from t_out back to t_in
                   (out-states U_out, V_out) or from t_in forward to t_out
-                  (in-states U_in, V_in).
+                  (in-states U_in, V_in); or with the paper's Dopri5
+                  tableau at a fixed step; or in the interaction picture
+                  (Lawson's integrating-factor RK4: the free evolution
+                  exp(-i H0(k) tau) exact in Fourier space).
 * ``observables`` inner products at the end of a run: the pair amplitude of
                   eq. (Nmn) in both of its forms, electron/positron marginals,
                   norm/orthogonality diagnostics.
@@ -41,7 +44,9 @@ something other than itself: Clifford algebra and spinor identities, the
 closed-form pure-gauge scattered wave, the Sauter-pulse pair spectrum,
 brute-force full-wave-function evolution with scipy's DOP853, unitarity and
 orthogonality identities, charge-conjugation symmetry, RK4 convergence
-order; for in-states, the pure-gauge closed form, the time independence of
+order; for the interaction picture, scipy's matrix exponential of H0(k),
+a free plane wave stepped exactly at any step size, order-4 convergence to
+the classical stepper's solution; for in-states, the pure-gauge closed form, the time independence of
 in/out overlaps (an in-state read at t_out against an out-state read at
 t_in) and the in/out balance of marginals over a complete lattice; the
 exact spin structure of the BW amplitude for E(t,x) fields and

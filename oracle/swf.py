@@ -19,7 +19,11 @@ for V).  Time integration: classical RK4 (reading of the paper's adaptive
 Dopri5 for the fixed-dt workloads) with step h = -dt from t_out, t_n = t_out -
 n dt, for out-states, and h = +dt from t_in, t_n = t_in + n dt, for in-states,
 the times evaluated from the step index; or the paper's Dopri5 (the
-Dormand-Prince 5(4) tableau) with the same fixed step (window.scheme "dp5").
+Dormand-Prince 5(4) tableau) with the same fixed step (window.scheme "dp5");
+or, as a variant stepper, the interaction picture (window.scheme "iprk4"):
+Lawson's integrating-factor RK4 (J. D. Lawson, SIAM J. Numer. Anal. 4 (1967)
+372), which takes the free evolution exp(-i H0(k) tau) exactly in Fourier
+space and integrates only the field terms with the classical RK4 tableau.
 """
 from __future__ import annotations
 
@@ -60,7 +64,7 @@ class SWFSolve:
         self.solve = sv
         self.forward = sv.kind >= 2     # in-states run forward from t_in
         self.scheme = getattr(problem.window, "scheme", "rk4")
-        if self.scheme not in ("rk4", "dp5"):
+        if self.scheme not in ("rk4", "dp5", "iprk4"):
             raise ValueError(f"unknown time stepper {self.scheme!r}")
         self.grid = problem.grids[sv.grid]
         self.terms = problem.fields[sv.field]
@@ -94,8 +98,24 @@ class SWFSolve:
     def kinetic(self, psi):
         return self.lat.ifft(-1j * apply(self.H0, self.lat.fft(psi)))
 
+    def field_terms(self, t: float, psi):
+        """The right-hand side without the kinetic term: -i V(t) (psi + psi_b)."""
+        return -1j * apply(self.potential_matrix(t), psi + self.psi_back(t))
+
     def rhs(self, t: float, psi):
-        return self.kinetic(psi) - 1j * apply(self.potential_matrix(t), psi + self.psi_back(t))
+        return self.kinetic(psi) + self.field_terms(t, psi)
+
+    # -- the free evolution, exactly ----------------------------------------
+    def free_propagator(self, tau: float):
+        """exp(-i H0(k) tau) per Fourier mode: H0(k)^2 = E_k^2, so the
+        exponential series sums to cos(E_k tau) - i sin(E_k tau) H0(k) / E_k."""
+        I = dirac.I4.reshape((4, 4) + (1,) * self.lat.dim)
+        return np.cos(self.Ek * tau)[None, None] * I - \
+            1j * (np.sin(self.Ek * tau) / self.Ek)[None, None] * self.H0
+
+    def free_evolve(self, psi, tau: float):
+        """psi evolved by the free Dirac equation d_t psi = -i H0 psi over tau."""
+        return self.lat.ifft(apply(self.free_propagator(tau), self.lat.fft(psi)))
 
     # -- classical RK4, h = -dt (out) or +dt (in) -------------------------
     def time(self, n: int) -> float:
@@ -115,6 +135,8 @@ class SWFSolve:
         of the stages."""
         if self.scheme == "dp5":
             return self._dp5_stages(n, y)[:4]
+        if self.scheme == "iprk4":
+            return self._iprk4_stages(n, y)
         h = self.window.dt if self.forward else -self.window.dt
         t = self.time(n)
         y1 = y
@@ -126,6 +148,37 @@ class SWFSolve:
         y4 = y + h * k3
         k4 = self.rhs(t + h, y4)
         ynew = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        if self.mask is not None:
+            ynew = ynew * self.mask[None]
+        return ynew, (y1, y2, y3, y4), (t, t + 0.5 * h, t + 0.5 * h, t + h), (1 / 6, 1 / 3, 1 / 3, 1 / 6)
+
+    # -- interaction picture: Lawson's integrating-factor RK4 ------------------
+    def _iprk4_stages(self, n: int, y):
+        """One step of d_t y = L y + N(t, y), L = -i H0 taken exactly: with
+        phi = exp(-L (t - t_n)) y the classical RK4 tableau is applied to
+        d_t phi = exp(-L (t - t_n)) N(t, exp(L (t - t_n)) phi) and the result
+        mapped back.  With P(tau) = exp(L tau):
+            k1 = N(t, y)
+            k2 = N(t + h/2, P(h/2) (y + h/2 k1))
+            k3 = N(t + h/2, P(h/2) y + h/2 k2)
+            k4 = N(t + h, P(h) y + h P(h/2) k3)
+            y_{n+1} = P(h) y + h/6 (P(h) k1 + 2 P(h/2) k2 + 2 P(h/2) k3 + k4).
+        The stage inputs (the arguments of N) are approximations of psi at
+        the stage times in the original picture, so the augmented BW integral
+        takes them with the RK4 weights, as for the classical stepper."""
+        h = self.window.dt if self.forward else -self.window.dt
+        t = self.time(n)
+        P = lambda v, tau: self.free_evolve(v, tau)  # noqa: E731
+        N = self.field_terms
+        y1 = y
+        k1 = N(t, y1)
+        y2 = P(y + 0.5 * h * k1, 0.5 * h)
+        k2 = N(t + 0.5 * h, y2)
+        y3 = P(y, 0.5 * h) + 0.5 * h * k2
+        k3 = N(t + 0.5 * h, y3)
+        y4 = P(y, h) + h * P(k3, 0.5 * h)
+        k4 = N(t + h, y4)
+        ynew = P(y, h) + (h / 6.0) * (P(k1, h) + 2.0 * P(k2, 0.5 * h) + 2.0 * P(k3, 0.5 * h) + k4)
         if self.mask is not None:
             ynew = ynew * self.mask[None]
         return ynew, (y1, y2, y3, y4), (t, t + 0.5 * h, t + 0.5 * h, t + h), (1 / 6, 1 / 3, 1 / 3, 1 / 6)

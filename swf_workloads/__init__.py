@@ -101,7 +101,8 @@ class Window:
     t_in: float
     t_out: float
     dt: float
-    scheme: str = "rk4"    # time stepper: "rk4" (classical) or "dp5" (Dormand-Prince 5, fixed step)
+    scheme: str = "rk4"    # time stepper: "rk4" (classical), "dp5" (Dormand-Prince 5, fixed step)
+                           # or "iprk4" (interaction picture: Lawson's integrating-factor RK4)
 
     @property
     def steps(self) -> int:
