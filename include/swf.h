@@ -158,7 +158,16 @@ typedef struct {
                                arrays per solve; no embedded error estimate or step
                                control).  BW integrals take the tableau's weights over
                                the stages.  SWF_DP5 does not combine with bw_partial or
-                               the persistent 1D kernel (the pass path runs instead)    */
+                               the persistent 1D kernel (the pass path runs instead).
+                               SWF_IPRK4: the interaction picture, Lawson's
+                               integrating-factor RK4 (J. D. Lawson, SIAM J. Numer.
+                               Anal. 4 (1967) 372): the free evolution exp(-i H0(k) h/2)
+                               exact in Fourier space, the field terms -i V (psi_s +
+                               psi_b) by the classical tableau; five free-evolution
+                               transforms of a whole state per step, six state arrays
+                               per solve, BW integrals with the RK4 weights over its
+                               stage inputs; not with bw_partial or the persistent 1D
+                               kernel                                                   */
     int graph_steps;        /* with use_graph: > 1 also captures that many consecutive
                                time steps as one graph, replayed while at least that
                                many steps remain (the one-step graph takes the rest,
@@ -166,7 +175,7 @@ typedef struct {
                                per graph                                                */
 } swf_options;
 
-typedef enum { SWF_RK4 = 0, SWF_DP5 = 1 } swf_stepper;
+typedef enum { SWF_RK4 = 0, SWF_DP5 = 1, SWF_IPRK4 = 2 } swf_stepper;
 
 /* Device bytes swf_init needs for these inputs (tables, states, scratch). */
 swf_status swf_workspace_size(const swf_grid* grids, int n_grids, const swf_term* terms,

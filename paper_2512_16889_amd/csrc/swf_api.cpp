@@ -190,6 +190,7 @@ struct Plan {
     double t0 = 0, sdt = 0, t_obs = 0;
     // time stepper: classical RK4 (4 stages) or fixed-step Dormand-Prince 5(4) (6 stages)
     bool dp5 = false;
+    bool ip = false;                    // interaction-picture stepper (Lawson's integrating-factor RK4)
     int nst = 4;
     double cst[6] = {}, wst[6] = {};   // stage nodes and quadrature weights
     std::vector<SolveDev> hs;           // buf pointers filled after allocation (offsets meanwhile)
@@ -276,7 +277,7 @@ static void add_items(Plan& P, Group& g, int fp64) {
 
 // State arrays of solve i: Y, ACC, YS, T; A0, A1 for the partial-integration
 // BW route; all eight (the Dormand-Prince slopes) with that stepper.
-static int nbufs(const Plan& P, size_t i) { return P.dp5 ? swf::NBUF : (P.aux[i] ? 6 : 4); }
+static int nbufs(const Plan& P, size_t i) { return P.dp5 ? swf::NBUF : (P.aux[i] || P.ip ? 6 : 4); }
 
 static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_grids, const swf_term* terms,
                       const int* ffirst, int n_fields, const swf_solve* solves, int n_solves,
@@ -299,9 +300,12 @@ static int build_plan(Plan& P, std::string& err, const swf_grid* grids, int n_gr
     P.t0 = P.forward ? win->t_in : win->t_out;
     P.sdt = P.forward ? -win->dt : win->dt;
     P.t_obs = P.forward ? win->t_out : win->t_in;
-    if (opt->stepper != SWF_RK4 && opt->stepper != SWF_DP5) FAIL(SWF_E_ARG, "stepper must be SWF_RK4 or SWF_DP5");
+    if (opt->stepper != SWF_RK4 && opt->stepper != SWF_DP5 && opt->stepper != SWF_IPRK4)
+        FAIL(SWF_E_ARG, "stepper must be SWF_RK4, SWF_DP5 or SWF_IPRK4");
     P.dp5 = opt->stepper == SWF_DP5;
+    P.ip = opt->stepper == SWF_IPRK4;
     if (P.dp5 && opt->bw_partial) FAIL(SWF_E_UNSUPPORTED, "the Dormand-Prince stepper does not combine with bw_partial");
+    if (P.ip && opt->bw_partial) FAIL(SWF_E_UNSUPPORTED, "the interaction-picture stepper does not combine with bw_partial");
     P.nst = P.dp5 ? 6 : 4;
     for (int st = 0; st < P.nst; ++st) {
         P.cst[st] = P.dp5 ? swf::dp5_c(st) : (st == 0 ? 0.0 : st == 3 ? 1.0 : 0.5);
@@ -848,7 +852,7 @@ static int launch(swf_ctx* ctx, const void* fn, int nitems, size_t it, int threa
 
 // x-axis pass of a group in the given mode (ROW_STAGE: the RK4 stage pass).
 static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, int dst, double tex, long long ph2,
-                    int kind = 4) {
+                    int kind = 4, int expo = 0, double tau = 0.0) {
     const auto* k = g.k[0];
     swf::PassArgs a = pass_args(ctx);
     a.stage = stage;
@@ -857,6 +861,8 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
     a.t_explicit = tex;
     a.ph2 = ph2;
     a.h0row = ctx->P.grids[g.grid].dim == 1 ? 1 : 0;
+    a.expo = expo;
+    a.tau = tau;
     double trav = 2;
     if (mode == swf::ROW_STAGE) {
         // stage input, the G buffer (2D, 3D), the RK4 operand and outputs; for
@@ -877,11 +883,14 @@ static int row_pass(swf_ctx* ctx, const Group& g, int mode, int stage, int src, 
 }
 
 // Whole-state column transform of a group along `axis` (in place on `role`).
-static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, int kind = 4) {
+static int col_pass(swf_ctx* ctx, const Group& g, int axis, int mode, int role, int kind = 4, int expo = 0,
+                    double tau = 0.0) {
     const auto& cv = g.k[axis]->col;
     swf::PassArgs a = pass_args(ctx);
     a.dst = role;
     a.src = role;
+    a.expo = expo;
+    a.tau = tau;
     const int n = axis == 1 ? g.n_ocy : g.n_ocz;
     const size_t it = axis == 1 ? g.it_ocy : g.it_ocz;
     return launch(ctx, cv.fn[axis - 1][mode], n, it, cv.threads, cv.lds, a, kind,
@@ -1068,8 +1077,103 @@ static int bw2_accum(swf_ctx* ctx) {
     return SWF_OK;
 }
 
+// ---- interaction picture (Lawson's integrating-factor RK4)
+// The free evolution exp(-i H0 tau) of a whole state, in place: the forward x
+// transform into the work buffer T, the column transforms with the propagator
+// applied on the last axis (in the inverse x transform for 1D), the inverse x
+// transform back.
+static int free_evolve(swf_ctx* ctx, const Group& g, int role, double tau) {
+    const int dim = ctx->P.grids[g.grid].dim;
+    int r = row_pass(ctx, g, swf::ROW_FWD, 0, role, swf::BUF_T, 0, 0);
+    if (!r && dim == 2) r = col_pass(ctx, g, 1, swf::COL_H0, swf::BUF_T, 4, 1, tau);
+    if (!r && dim == 3) {
+        r = col_pass(ctx, g, 1, swf::COL_FWD, swf::BUF_T);
+        if (!r) r = col_pass(ctx, g, 2, swf::COL_H0, swf::BUF_T, 4, 1, tau);
+        if (!r) r = col_pass(ctx, g, 1, swf::COL_INV, swf::BUF_T);
+    }
+    if (!r) r = row_pass(ctx, g, swf::ROW_INV, 0, role, role, 0, 0, 4, 1, tau);
+    return r;
+}
+
+// out_j = sum_i c[j][i] in_i over a group's states (roles; -1 unused).
+static int combo(swf_ctx* ctx, const Group& g, const int (&in)[3], const int (&out)[2], const double (&c)[2][3],
+                 int mask = 0) {
+    swf::ComboArgs a;
+    memset(&a, 0, sizeof(a));
+    a.solves = ctx->d_solves();
+    a.items = ctx->d_items() + g.it_orow;
+    a.rows = g.k[0]->row0_rows;
+    a.rtab = ctx->d_rtab();
+    for (int i = 0; i < 3; ++i) {
+        a.in[i] = in[i];
+        a.c[0][i] = c[0][i];
+        a.c[1][i] = c[1][i];
+    }
+    a.out[0] = out[0];
+    a.out[1] = out[1];
+    a.mask = mask;
+    HIPCHK(swf::launch_combo(ctx->P.fp64, a, g.n_orow, ctx->st));
+    return SWF_OK;
+}
+
+// One step: with h the signed step, E = exp(-i H0 h/2) and N(t, y) = -i V(t) (y + psi_b),
+//   k1 = N(t, y),                a = E (y + h/2 k1),
+//   k2 = N(t + h/2, a),          b = E y + h/2 k2,
+//   k3 = N(t + h/2, b),          c = E (E y + h k3),
+//   k4 = N(t + h, c),            y' = E (E (y + h/6 k1) + h/3 (k2 + k3)) + h/6 k4
+// (= E^2 y + h/6 (E^2 k1 + 2 E k2 + 2 E k3 + k4)).  The stage inputs y, a, b, c
+// pass through YS (y itself at stage 0) so that the BW reductions read them as
+// for the classical stepper; ACC carries the update, A0 the sum k2 + k3, A1 the
+// latest slope, T is the transforms' work buffer.
+static int ip_step(swf_ctx* ctx) {
+    using namespace swf;
+    const double h = -ctx->P.sdt;
+    auto each = [&](auto&& f) {
+        for (const auto& g : groups(ctx)) {
+            int r = f(g);
+            if (r) return r;
+        }
+        return (int)SWF_OK;
+    };
+    int r = bw_stage(ctx, 0);
+    if (!r) r = each([&](const Group& g) {
+        int rr = row_pass(ctx, g, ROW_SRC, 0, BUF_Y, BUF_A1, 0, 0);
+        if (!rr) rr = combo(ctx, g, {BUF_Y, BUF_A1, -1}, {BUF_YS, BUF_ACC}, {{1.0, 0.5 * h, 0.0}, {1.0, h / 6.0, 0.0}});
+        if (!rr) rr = free_evolve(ctx, g, BUF_YS, 0.5 * h);   // a
+        if (!rr) rr = free_evolve(ctx, g, BUF_Y, 0.5 * h);    // E y
+        return rr;
+    });
+    if (!r) r = bw_stage(ctx, 1);
+    if (!r) r = each([&](const Group& g) {
+        int rr = row_pass(ctx, g, ROW_SRC, 1, BUF_YS, BUF_A1, 0, 0);
+        if (!rr) rr = combo(ctx, g, {BUF_Y, BUF_A1, -1}, {BUF_YS, BUF_A0}, {{1.0, 0.5 * h, 0.0}, {0.0, 1.0, 0.0}});   // b, k2
+        return rr;
+    });
+    if (!r) r = bw_stage(ctx, 2);
+    if (!r) r = each([&](const Group& g) {
+        int rr = row_pass(ctx, g, ROW_SRC, 2, BUF_YS, BUF_A1, 0, 0);
+        if (!rr) rr = combo(ctx, g, {BUF_Y, BUF_A1, BUF_A0}, {BUF_YS, BUF_A0}, {{1.0, h, 0.0}, {0.0, 1.0, 1.0}});
+        if (!rr) rr = free_evolve(ctx, g, BUF_YS, 0.5 * h);   // c
+        if (!rr) rr = free_evolve(ctx, g, BUF_ACC, 0.5 * h);
+        if (!rr) rr = combo(ctx, g, {BUF_ACC, BUF_A0, -1}, {BUF_ACC, -1}, {{1.0, h / 3.0, 0.0}, {0.0, 0.0, 0.0}});
+        if (!rr) rr = free_evolve(ctx, g, BUF_ACC, 0.5 * h);
+        return rr;
+    });
+    if (!r) r = bw_stage(ctx, 3);
+    if (!r) r = each([&](const Group& g) {
+        int rr = row_pass(ctx, g, ROW_SRC, 3, BUF_YS, BUF_A1, 0, 0);
+        if (!rr) rr = combo(ctx, g, {BUF_ACC, BUF_A1, -1}, {BUF_Y, -1}, {{1.0, h / 6.0, 0.0}, {0.0, 0.0, 0.0}}, 1);
+        return rr;
+    });
+    if (!r) r = bw_accum(ctx);
+    if (r) return r;
+    HIPCHK(swf::launch_tick(ctx->d_step(), ctx->st));
+    return SWF_OK;
+}
+
 // Enqueue one full RK4 step of every solve.
 static int enqueue_step(swf_ctx* ctx) {
+    if (ctx->P.ip) return ip_step(ctx);
     if (ctx->opt.batched && ctx->opt.chunk > 0 && ctx->P.hv.empty()) {
         // chunk-major: all stages of one chunk before the next chunk
         for (const auto& g : groups(ctx))
@@ -1122,7 +1226,7 @@ static int line_build(const swf_ctx* ctx, const Group& g) {
 // kernel whose LDS (with the group's field terms) fits, and no vertex couples
 // two solves.
 static bool line_path(swf_ctx* ctx) {
-    if (!ctx->opt.persistent || !ctx->P.hv.empty() || ctx->P.dp5) return false;
+    if (!ctx->opt.persistent || !ctx->P.hv.empty() || ctx->P.dp5 || ctx->P.ip) return false;
     for (const auto& g : groups(ctx))
         if (line_build(ctx, g) < 0) return false;
     return true;
@@ -1800,7 +1904,7 @@ swf_status swf_init(const swf_grid* grids, int n_grids, const swf_term* terms, c
                 g.vy = g.k[1] ? std::min(v, g.k[1]->nvar - 1) : 0;
                 g.vz = g.k[2] ? std::min(v, g.k[2]->nvar - 1) : 0;
             }
-    } else if (opt->tune && !line_path(ctx)) {
+    } else if (opt->tune && !line_path(ctx) && !ctx->P.ip) {   // (the interaction picture runs no stage pass)
         int rr = autotune(ctx, ctx->opt.batched ? ctx->P.batched : ctx->P.single);
         if (rr) return fail(rr);
     }

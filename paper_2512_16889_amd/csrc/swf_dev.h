@@ -421,6 +421,25 @@ __device__ __forceinline__ void apply_h0(C& p0, C& p1, C& p2, C& p3, decltype(C:
     (void)sizeof(R);
 }
 
+// The free evolution over tau of one Fourier mode, times s:
+// exp(-i H0(K) tau) = cos(E tau) - i sin(E tau) H0(K) / E with E = sqrt(1 + K^2)
+// (H0^2 = E^2); E and the angle in double.
+template <class C>
+__device__ __forceinline__ void apply_expo(C& p0, C& p1, C& p2, C& p3, double Kx, double Ky, double Kz, double tau,
+                                           double s) {
+    using R = decltype(C::x);
+    const double E = sqrt(1.0 + Kx * Kx + Ky * Ky + Kz * Kz);
+    double sn, cs;
+    sincos(E * tau, &sn, &cs);
+    C q0 = p0, q1 = p1, q2 = p2, q3 = p3;
+    apply_h0(q0, q1, q2, q3, (R)Kx, (R)Ky, (R)Kz, (R)(s * sn / E));
+    const R c = (R)(s * cs);
+    p0 = cadd(cscale(p0, c), q0);
+    p1 = cadd(cscale(p1, c), q1);
+    p2 = cadd(cscale(p2, c), q2);
+    p3 = cadd(cscale(p3, c), q3);
+}
+
 // (A_0 + alpha^j A_j) s for one site; A1..A3 covariant components.
 template <class C>
 __device__ __forceinline__ void apply_pot(const C (&s)[4], C (&o)[4], decltype(C::x) A0, decltype(C::x) A1,

@@ -46,6 +46,8 @@ struct PassArgs {
     int stage;             // RK4 stage 0..3 (ROW_STAGE, ROW_SRC)
     int src, dst;          // buffer roles
     int h0row;             // 1: the row pass also applies -i H0 / N (dim == 1)
+    int expo;              // 1: the k-space multiply (COL_H0, h0row) is exp(-i H0 tau) / N instead
+    double tau;            //    of -i H0 / N: the free evolution over tau (interaction picture)
     double t_explicit;     // time of ROW_RHS
     long long ph2;         // ROW_FWDPH: complex offset of exp(i k_j x_j) tables
     int nitems;            // work items of this launch
@@ -251,10 +253,17 @@ __global__ void __launch_bounds__((RowVar<R, N, V>::THREADS)) row_kernel(PassArg
             if (a.h0row) {
                 const R Ky = (R)S->kap[1], Kz = (R)S->kap[2], s = (R)S->inv_n;
                 const double dk = S->dk[0];
+                if (a.expo) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const R Kx = (R)(dk * kindex(t + T * m, N));
-                    apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+                    for (int m = 0; m < E; ++m)
+                        apply_expo(v[0][m], v[1][m], v[2][m], v[3][m], dk * kindex(t + T * m, N), S->kap[1], S->kap[2],
+                                   a.tau, S->inv_n);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const R Kx = (R)(dk * kindex(t + T * m, N));
+                        apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+                    }
                 }
             }
             fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, line, tw);
@@ -378,20 +387,20 @@ __global__ void __launch_bounds__((ColVar<R, N, V>::THREADS)) col_kernel(PassArg
     }
     if constexpr (MODE == COL_FWD || MODE == COL_H0) fft4<C, N, T, -1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);
     if constexpr (MODE == COL_H0) {
-        const R s = (R)S->inv_n;
-        const R Kx = (R)(S->dk[0] * kindex(act ? x : 0, n0));
+        const double kx = S->dk[0] * kindex(act ? x : 0, n0);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int idx = t + T * m;
-            R Ky, Kz;
+            double ky, kz;
             if constexpr (AXIS == 1) {
-                Ky = (R)(S->dk[1] * kindex(idx, N));
-                Kz = (R)S->kap[2];
+                ky = S->dk[1] * kindex(idx, N);
+                kz = S->kap[2];
             } else {
-                Ky = (R)(S->dk[1] * kindex(other, n1));
-                Kz = (R)(S->dk[2] * kindex(idx, N));
+                ky = S->dk[1] * kindex(other, n1);
+                kz = S->dk[2] * kindex(idx, N);
             }
-            apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], Kx, Ky, Kz, s);
+            if (a.expo) apply_expo(v[0][m], v[1][m], v[2][m], v[3][m], kx, ky, kz, a.tau, S->inv_n);
+            else apply_h0(v[0][m], v[1][m], v[2][m], v[3][m], (R)kx, (R)ky, (R)kz, (R)S->inv_n);
         }
     }
     if constexpr (MODE == COL_INV || MODE == COL_H0) fft4<C, N, T, +1, CG, VC::SEQ, Lay, typename VC::PL>(v, lds, t, xl, tw);

@@ -112,6 +112,21 @@ struct PairArgs {
     double2* part;       // [mp][np][splits] partial tiles, then [mp][np] the sum
 };
 
+// Pointwise combination of state arrays of a group's solves (the interaction
+// picture's stage inputs and update): out_j = sum_i c[j][i] in_i over every
+// site and component, optionally times the absorber mask.
+struct ComboArgs {
+    const SolveDev* solves;
+    const int2* items;   // (solve, block of `rows` x-lines) per workgroup
+    int rows;
+    const void* rtab;    // real tables (the masks)
+    int in[3];           // input roles (-1: unused)
+    int out[2];          // output roles (-1: unused)
+    double c[2][3];
+    int mask;            // 1: output 0 is multiplied by the solve's absorber mask (if it has one)
+};
+hipError_t launch_combo(int fp64, const ComboArgs& a, int nitems, hipStream_t st);
+
 hipError_t launch_reduction(int fp64, int kind, const RedArgs& a, int blocks, hipStream_t st);
 hipError_t launch_pair_gemm(int fp64, const PairArgs& a, hipStream_t st);
 // a.groups: ngroups consecutive groups, all of nu U and nv V solves (1 or 2 each)

@@ -746,6 +746,49 @@ hipError_t launch_bw2_accum(const BwArgs& a, int nblk, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class R>
+__global__ void __launch_bounds__(RED_THREADS) combo_kernel(ComboArgs a) {
+    using C = cpx<R>;
+    const int2 it = a.items[blockIdx.x];
+    const SolveDev* __restrict__ S = a.solves + it.x;
+    const int n0 = S->n[0], n1 = S->n[1], nrows = S->nrows;
+    const long long ns = S->nsites;
+    gptr<const nv2<R>> in[3];
+    R c[2][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        in[i] = a.in[i] >= 0 ? cview<R>(S->buf[a.in[i]]) : cview<R>(S->buf[0]);
+        c[0][i] = (R)a.c[0][i];
+        c[1][i] = (R)a.c[1][i];
+    }
+    gptr<nv2<R>> o0 = wview<R>(S->buf[a.out[0] >= 0 ? a.out[0] : 0]);
+    gptr<nv2<R>> o1 = wview<R>(S->buf[a.out[1] >= 0 ? a.out[1] : 0]);
+    gptr<const R> rtab = glob(reinterpret_cast<const R*>(a.rtab));
+    const bool mask = a.mask && S->mask >= 0;
+    const int per = a.rows * n0;
+    for (int e = threadIdx.x; e < 4 * per; e += RED_THREADS) {
+        const int q = e / per, r = e % per;
+        const int row = it.y * a.rows + r / n0, x = r % n0;
+        if (row >= nrows) continue;
+        const long long idx = (long long)q * ns + (long long)row * n0 + x;
+        C v[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = a.in[i] >= 0 ? gload_nt<C>(in[i], idx) : cmake<C>((R)0, (R)0);
+        C w0 = cadd(cadd(cscale(v[0], c[0][0]), cscale(v[1], c[0][1])), cscale(v[2], c[0][2]));
+        if (mask) w0 = cscale(w0, rtab[S->mask + x] * rtab[S->mask + n0 + row % n1] * rtab[S->mask + n0 + n1 + row / n1]);
+        if (a.out[0] >= 0) gstore_nt<C>(o0, idx, w0);
+        if (a.out[1] >= 0)
+            gstore_nt<C>(o1, idx, cadd(cadd(cscale(v[0], c[1][0]), cscale(v[1], c[1][1])), cscale(v[2], c[1][2])));
+    }
+}
+
+hipError_t launch_combo(int fp64, const ComboArgs& a, int nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (fp64) hipLaunchKernelGGL(combo_kernel<double>, dim3(nitems), dim3(RED_THREADS), 0, st, a);
+    else hipLaunchKernelGGL(combo_kernel<float>, dim3(nitems), dim3(RED_THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tick(int* step, hipStream_t st) { return launch_advance(step, 1, st); }
 
 hipError_t launch_finite_check(int fp64, const SolveDev* solves, int nsolves, int step, unsigned long long* flag,

@@ -29,8 +29,8 @@ _lib = C.CDLL(LIB_PATH)
 
 SWF_OK, SWF_E_ARG, SWF_E_NOMEM, SWF_E_HIP, SWF_E_ORDER, SWF_E_UNSUPPORTED, SWF_E_NONFINITE = range(7)
 SWF_FP64, SWF_MIXED = 0, 1
-SWF_RK4, SWF_DP5 = 0, 1
-STEPPERS = {"rk4": SWF_RK4, "dp5": SWF_DP5}
+SWF_RK4, SWF_DP5, SWF_IPRK4 = 0, 1, 2
+STEPPERS = {"rk4": SWF_RK4, "dp5": SWF_DP5, "iprk4": SWF_IPRK4}
 AMP_PAIR1, AMP_PAIR2, AMP_BW, AMP_BW_PARTIAL = 0, 1, 2, 3
 P_MARGINAL_E, P_MARGINAL_POS, P_PAIR, P_BW = 0, 1, 2, 3
 STAT_ROW, STAT_COLY, STAT_COLZ, STAT_BW, STAT_OTHER = range(5)

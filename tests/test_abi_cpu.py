@@ -143,5 +143,8 @@ def test_stepper_validation(S):
     c5, b5 = size(stepper=S.SWF_DP5)
     assert c4 == 0 and c5 == 0 and b5 > b4            # eight state arrays per solve instead of four
     assert size(stepper=S.SWF_DP5, bw_partial=1)[0] == S.SWF_E_UNSUPPORTED
+    cip, bip = size(stepper=S.SWF_IPRK4)
+    assert cip == 0 and b4 < bip < b5                 # six state arrays per solve
+    assert size(stepper=S.SWF_IPRK4, bw_partial=1)[0] == S.SWF_E_UNSUPPORTED
     assert size(stepper=7)[0] == S.SWF_E_ARG
     assert S.workspace_size(prob) == b5               # the binding takes the stepper from the window
