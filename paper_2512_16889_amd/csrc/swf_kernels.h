@@ -472,95 +472,142 @@ __global__ void __launch_bounds__((CdVar<R, N, V>::THREADS)) col_d_kernel(PassAr
     // (the persistent loop only for the y pass: the z pass's partial sums would
     // double the registers a prefetch holds)
     constexpr bool PIPE = VC::PIPE && !ACCUM;
-    // Every solve of a launch has the same lengths (so the same twiddles); a
-    // tile's own descriptor words (its item and its solve's arrays) are read
-    // through the constant address space, as scalar loads, which do not wait
-    // for the previous tile's stores still in flight.
-    const SolveDev* S0 = a.solves + a.items[blockIdx.x].x;
-    const int n0 = S0->n[0], n1 = S0->n[1];
-    const int ntx = (n0 + W - 1) / W;
-    const long long ns = S0->nsites;
-    const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
-    const double kscale = S0->dk[AXIS] / (double)N;
-    gptr<const nv2<R>> ctab = cview<R>(a.ctab);
-    for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S0->tw[AXIS] + i);
-    using cword = const unsigned long long __attribute__((address_space(4)))*;
-    struct Tile {
-        unsigned long long src, dst;   // the solve's stage input and G arrays
-        long long base;
-        bool act;
-    };
-    auto tile = [&](int item) {
-        const unsigned long long w = *(cword)(a.items + item);
-        const int solve = (int)(unsigned)w, ty = (int)(w >> 32);
-        const int other = ty / ntx;
-        const int x = (ty % ntx) * W + xl;
-        Tile u;
-        // (no partial persistent tiles: their stores need no branch)
-        u.act = PIPE || x < n0;
+    if constexpr (!PIPE) {
+        // one tile = W adjacent columns of one solve at one fixed other-axis index
+        const int2 it = a.items[blockIdx.x];
+        const SolveDev* __restrict__ S = a.solves + it.x;
+        const int n0 = S->n[0], n1 = S->n[1];
+        const int ntx = (n0 + W - 1) / W;
+        const int other = it.y / ntx;
+        const int x = (it.y % ntx) * W + xl;
+        const bool act = x < n0;
+        const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
         const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
-        u.base = obase + (u.act ? x : 0) + (long long)t * stride;
-        const SolveDev* S = a.solves + solve;
-        u.src = *(cword)(&S->buf[a.src]);
-        u.dst = *(cword)(&S->buf[a.dst]);
-        return u;
-    };
-    auto load = [&](const Tile& u, C (&v)[E], C (&g)[E]) {
-        gptr<const nv2<R>> p = cview<R>((const void*)u.src) + u.base + src * ns;
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = gload_nt<C>(p, (long long)(T * m) * stride);
-        if constexpr (ACCUM) {
-            // the partial sum of the earlier axis, loaded ahead of the transforms
-            gptr<const nv2<R>> pg = cview<R>((const void*)u.dst) + u.base + q * ns;
-#pragma unroll
-            for (int m = 0; m < E; ++m) g[m] = gload_nt<C>(pg, (long long)(T * m) * stride);
-        }
-    };
+        const long long base = obase + (act ? x : 0) + (long long)t * stride;
+        const long long ns = S->nsites;
+        gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+        for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S->tw[AXIS] + i);
 
-    // Order of a persistent iteration: issue the next tile's loads, transform
-    // this tile, store it, then take the next tile's values (waiting for its
-    // loads but not for the stores just issued).  The first tile's loads are
-    // waited for before the loop, so that at the loop's top only stores are
-    // in flight and nothing there waits for them.
-    int item = blockIdx.x;
-    Tile u = tile(item);
-    C v[1][E], g[E];
-    load(u, v[0], g);
-    if constexpr (PIPE) {
+        C v[1][E];
+        C g[E];
+        {
+            gptr<const nv2<R>> p = cview<R>(S->buf[a.src]) + base + src * ns;
 #pragma unroll
-        for (int m = 0; m < E; ++m) asm volatile("" ::"v"(v[0][m].x), "v"(v[0][m].y));
-    }
-    for (;;) {
-        const int next = item + (int)gridDim.x;
-        const bool more = PIPE && next < a.nitems;
-        Tile un;
-        C vn[E], gn[E];
-        if (more) {
-            un = tile(next);
-            load(un, vn, gn);
+            for (int m = 0; m < E; ++m) v[0][m] = gload_nt<C>(p, (long long)(T * m) * stride);
+            if constexpr (ACCUM) {
+                // the partial sum of the earlier axis, loaded ahead of the transforms
+                gptr<const nv2<R>> pg = cview<R>(S->buf[a.dst]) + base + q * ns;
+#pragma unroll
+                for (int m = 0; m < E; ++m) g[m] = gload_nt<C>(pg, (long long)(T * m) * stride);
+            }
         }
         fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+        const double kscale = S->dk[AXIS] / (double)N;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const C w = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
             v[0][m] = AXIS == 1 ? alpha2_phase(q, w) : alpha3_phase(q, w);
         }
         fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
-        if (u.act) {
-            gptr<nv2<R>> p = wview<R>((void*)u.dst) + u.base + q * ns;
+        if (act) {
+            gptr<nv2<R>> p = wview<R>(S->buf[a.dst]) + base + q * ns;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
                 gstore_nt<C>(p, (long long)(T * m) * stride, o);
             }
         }
-        if (!more) break;
-        item = next;
-        u = un;
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            v[0][m] = vn[m];
-            g[m] = gn[m];
+    } else {
+        // Every solve of a launch has the same lengths (so the same twiddles); a
+        // tile's own descriptor words (its item and its solve's arrays) are read
+        // through the constant address space, as scalar loads, which do not wait
+        // for the previous tile's stores still in flight.
+        const SolveDev* S0 = a.solves + a.items[blockIdx.x].x;
+        const int n0 = S0->n[0], n1 = S0->n[1];
+        const int ntx = (n0 + W - 1) / W;
+        const long long ns = S0->nsites;
+        const long long stride = AXIS == 1 ? (long long)n0 : (long long)n0 * n1;
+        const double kscale = S0->dk[AXIS] / (double)N;
+        gptr<const nv2<R>> ctab = cview<R>(a.ctab);
+        for (int i = tid; i < N; i += VC::THREADS) tw[i] = gload<C>(ctab, S0->tw[AXIS] + i);
+        using cword = const unsigned long long __attribute__((address_space(4)))*;
+        struct Tile {
+            unsigned long long src, dst;   // the solve's stage input and G arrays
+            long long base;
+            bool act;
+        };
+        auto tile = [&](int item) {
+            const unsigned long long w = *(cword)(a.items + item);
+            const int solve = (int)(unsigned)w, ty = (int)(w >> 32);
+            const int other = ty / ntx;
+            const int x = (ty % ntx) * W + xl;
+            Tile u;
+            // (no partial persistent tiles: their stores need no branch)
+            u.act = PIPE || x < n0;
+            const long long obase = AXIS == 1 ? (long long)other * n0 * n1 : (long long)other * n0;
+            u.base = obase + (u.act ? x : 0) + (long long)t * stride;
+            const SolveDev* S = a.solves + solve;
+            u.src = *(cword)(&S->buf[a.src]);
+            u.dst = *(cword)(&S->buf[a.dst]);
+            return u;
+        };
+        auto load = [&](const Tile& u, C (&v)[E], C (&g)[E]) {
+            gptr<const nv2<R>> p = cview<R>((const void*)u.src) + u.base + src * ns;
+    #pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = gload_nt<C>(p, (long long)(T * m) * stride);
+            if constexpr (ACCUM) {
+                // the partial sum of the earlier axis, loaded ahead of the transforms
+                gptr<const nv2<R>> pg = cview<R>((const void*)u.dst) + u.base + q * ns;
+    #pragma unroll
+                for (int m = 0; m < E; ++m) g[m] = gload_nt<C>(pg, (long long)(T * m) * stride);
+            }
+        };
+
+        // Order of a persistent iteration: issue the next tile's loads, transform
+        // this tile, store it, then take the next tile's values (waiting for its
+        // loads but not for the stores just issued).  The first tile's loads are
+        // waited for before the loop, so that at the loop's top only stores are
+        // in flight and nothing there waits for them.
+        int item = blockIdx.x;
+        Tile u = tile(item);
+        C v[1][E], g[E];
+        load(u, v[0], g);
+        if constexpr (PIPE) {
+    #pragma unroll
+            for (int m = 0; m < E; ++m) asm volatile("" ::"v"(v[0][m].x), "v"(v[0][m].y));
+        }
+        for (;;) {
+            const int next = item + (int)gridDim.x;
+            const bool more = PIPE && next < a.nitems;
+            Tile un;
+            C vn[E], gn[E];
+            if (more) {
+                un = tile(next);
+                load(un, vn, gn);
+            }
+            fft_line<C, N, T, -1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+    #pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const C w = cscale(v[0][m], (R)(kscale * kindex(t + T * m, N)));
+                v[0][m] = AXIS == 1 ? alpha2_phase(q, w) : alpha3_phase(q, w);
+            }
+            fft_line<C, N, T, +1, 1, 1, Lay, PL>(v, lds, t, xl, tw);
+            if (u.act) {
+                gptr<nv2<R>> p = wview<R>((void*)u.dst) + u.base + q * ns;
+    #pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const C o = ACCUM ? cadd(g[m], v[0][m]) : v[0][m];
+                    gstore_nt<C>(p, (long long)(T * m) * stride, o);
+                }
+            }
+            if (!more) break;
+            item = next;
+            u = un;
+    #pragma unroll
+            for (int m = 0; m < E; ++m) {
+                v[0][m] = vn[m];
+                g[m] = gn[m];
+            }
         }
     }
 }
