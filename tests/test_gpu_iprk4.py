@@ -148,3 +148,16 @@ def test_iprk4_errors(S):
     with pytest.raises(S.SwfError) as e:
         S.Context(prob, precision="fp64", bw_partial=True)
     assert e.value.code == S.SWF_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_iprk4_launch_config_2d_512_x64_pure_gauge(S, prec):
+    # the 2D workload's launch configuration (64 solves on 512^2) stepped by the
+    # interaction picture through a pure-gauge pulse: the scattered wave is
+    # (exp(-i Lambda) - 1) psi_back at every site, checked at sampled sites
+    from test_gpu_fullsize import pure_gauge_check
+    lam0, tau, w = 0.8, 4.0, 10.0
+    prob = W.config_2d(n_solves=64, t_half=60.0)
+    prob.fields = [W.field_pure_gauge(lam0, tau, w, 2)]
+    prob.window = W.Window(0.0, 24.0, 0.02, "iprk4")
+    pure_gauge_check(S, prob, lam0, tau, w, prec, prob.window.steps)
