@@ -22,7 +22,10 @@ strong-field processes in multidimensional background fields"):
                   (in-states U_in, V_in); or with the paper's Dopri5
                   tableau at a fixed step; or in the interaction picture
                   (Lawson's integrating-factor RK4: the free evolution
-                  exp(-i H0(k) tau) exact in Fourier space).
+                  exp(-i H0(k) tau) exact in Fourier space).  A variant
+                  derivative, the periodic central finite difference of
+                  order 2, 4 or 8 (``fd_order``), judges a stencil against
+                  the spectral derivative.
 * ``observables`` inner products at the end of a run: the pair amplitude of
                   eq. (Nmn) in both of its forms, electron/positron marginals,
                   norm/orthogonality diagnostics.

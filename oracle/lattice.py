@@ -12,13 +12,18 @@ import numpy as np
 
 
 class Lattice:
-    def __init__(self, grid):
+    def __init__(self, grid, fd_order: int = 0):
         self.dim = int(grid.dim)
         self.n = [int(grid.n[j]) for j in range(self.dim)]
         self.L = [float(grid.L[j]) for j in range(self.dim)]
         self.dx = [self.L[j] / self.n[j] for j in range(self.dim)]
         self.x1d = [-self.L[j] / 2 + np.arange(self.n[j]) * self.dx[j] for j in range(self.dim)]
         self.k1d = [2 * np.pi * np.fft.fftfreq(self.n[j], self.dx[j]) for j in range(self.dim)]
+        self.fd_order = fd_order
+        if fd_order:
+            # a periodic central finite-difference derivative is diagonal in Fourier
+            # space with the stencil's symbol in place of k
+            self.k1d = [fd_symbol(k, self.dx[j], fd_order) for j, k in enumerate(self.k1d)]
         self.X = np.meshgrid(*self.x1d, indexing="ij")
         self.K = np.meshgrid(*self.k1d, indexing="ij")
         self.dV = float(np.prod(self.dx))
@@ -62,3 +67,23 @@ class Lattice:
             shp[j] = self.n[j]
             m = m * mj.reshape(shp)
         return m
+
+
+def fd_coefficients(order: int):
+    """Weights a_1..a_p of the central first-derivative stencil of even order
+    2p, f'(x) ~ sum_m a_m (f(x + m dx) - f(x - m dx)) / dx: the unique
+    weights that make it exact for polynomials of degree 2p, in closed form
+    a_m = (-1)^(m+1) (p!)^2 / (m (p-m)! (p+m)!)."""
+    from math import factorial
+    if order < 2 or order % 2:
+        raise ValueError("the central stencil has an even order >= 2")
+    p = order // 2
+    return [(-1) ** (m + 1) * factorial(p) ** 2 / (m * factorial(p - m) * factorial(p + m)) for m in range(1, p + 1)]
+
+
+def fd_symbol(k, dx: float, order: int):
+    """The stencil's Fourier symbol: it maps exp(ikx) to i K(k) exp(ikx) with
+    K(k) = sum_m 2 a_m sin(m k dx) / dx (for any k, on or off the lattice)."""
+    k = np.asarray(k, dtype=float)
+    return sum(2.0 * a * np.sin(m * k * dx) for m, a in enumerate(fd_coefficients(order), start=1)) / dx
+

@@ -59,7 +59,13 @@ def apply(M, psi):
 class SWFSolve:
     """One solve (U_out, V_out, U_in or V_in of (s, p)) on its lattice."""
 
-    def __init__(self, problem, index: int):
+    def __init__(self, problem, index: int, fd_order: int = 0):
+        """fd_order > 0: the spatial derivative is the periodic central finite
+        difference of that (even) order instead of the spectral one, a variant
+        for judging a stencil against the paper's spectral derivative: the free
+        Hamiltonian becomes H0(K(k)) with K the stencil's symbol, and the
+        background is that Hamiltonian's plane-wave solution, the spinor and
+        energy of momentum K(p) on the lattice axes (the phase keeps p)."""
         sv = problem.solves[index]
         self.solve = sv
         self.forward = sv.kind >= 2     # in-states run forward from t_in
@@ -69,8 +75,13 @@ class SWFSolve:
         self.grid = problem.grids[sv.grid]
         self.terms = problem.fields[sv.field]
         self.window = problem.window
-        self.lat = Lattice(self.grid)
+        self.lat = Lattice(self.grid, fd_order)
         self.w, self.E, self.K = dirac.background_spinor(sv.kind, sv.spin, sv.p)
+        if fd_order:
+            from .lattice import fd_symbol
+            dim = self.grid.dim
+            p_eff = [float(fd_symbol(sv.p[j], self.lat.dx[j], fd_order)) if j < dim else sv.p[j] for j in range(3)]
+            self.w, self.E, _ = dirac.background_spinor(sv.kind, sv.spin, p_eff)
         lat = self.lat
         self.kfull = lat.full_momentum(self.K)
         self.H0 = sum(dirac.ALPHA[j][:, :, None] * self.kfull[j].reshape(1, 1, -1)
